@@ -1,0 +1,132 @@
+"""Test helpers: golden-file parsing, result comparison and independent
+certificate checks in exact rational arithmetic."""
+from __future__ import annotations
+
+import os
+from fractions import Fraction
+
+import numpy as np
+
+OPTIMAL, INFEASIBLE, UNBOUNDED, INVALID = 0, 1, 2, 3
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+# Parity bar: status bit-exact; for OPTIMAL LPs ||x - x_ref|| <= 1e-4 * max(1, ||x_ref||).
+X_RTOL = 1e-4
+
+
+def parse_golden(path):
+    lps, cur = [], None
+    with open(path) as f:
+        for raw in f:
+            line = raw.split("#", 1)[0].strip()
+            if not line:
+                continue
+            tok = line.split()
+            if tok[0] == "lp":
+                cur = {"name": tok[1], "rows": [], "c": None, "expect": None}
+            elif tok[0] == "c":
+                cur["c"] = (float(tok[1]), float(tok[2]))
+            elif tok[0] == "row":
+                cur["rows"].append(tuple(float(t) for t in tok[1:4]))
+            elif tok[0] == "expect":
+                st = {"optimal": OPTIMAL, "infeasible": INFEASIBLE, "unbounded": UNBOUNDED}[tok[1]]
+                xy = (float(tok[2]), float(tok[3])) if st == OPTIMAL else None
+                cur["expect"] = (st, xy)
+            elif tok[0] == "end":
+                lps.append(cur)
+                cur = None
+    return lps
+
+
+def golden_batch(path):
+    """Turn a golden file into a gen.Batch plus the expected (status, xy) list."""
+    from paper_1902_04995_amd import gen
+    lps = parse_golden(path)
+    sizes = [len(lp["rows"]) for lp in lps]
+    offs = np.zeros(len(lps) + 1, np.int64)
+    np.cumsum(sizes, out=offs[1:])
+    rows = np.array([r for lp in lps for r in lp["rows"]], np.float64).reshape(-1, 3)
+    bt = gen.Batch(offs, rows[:, 0].astype(np.float32), rows[:, 1].astype(np.float32),
+                   rows[:, 2].astype(np.float32),
+                   np.array([lp["c"][0] for lp in lps], np.float32),
+                   np.array([lp["c"][1] for lp in lps], np.float32),
+                   np.full(len(lps), gen.KIND_OTHER, np.int8), os.path.basename(path))
+    return bt, [lp["expect"] for lp in lps], [lp["name"] for lp in lps]
+
+
+def compare(status, x, y, ref_status, ref_x, ref_y, rtol=X_RTOL):
+    """Indices where (status, x) disagrees with the reference under the parity bar."""
+    status = np.asarray(status)
+    ref_status = np.asarray(ref_status)
+    bad_status = status != ref_status
+    opt = (ref_status == OPTIMAL) & ~bad_status
+    dx = np.hypot(np.asarray(x, np.float64) - ref_x, np.asarray(y, np.float64) - ref_y)
+    scale = np.maximum(1.0, np.hypot(ref_x, ref_y))
+    bad_x = np.zeros_like(bad_status)
+    bad_x[opt] = ~(dx[opt] <= rtol * scale[opt])
+    return np.flatnonzero(bad_status), np.flatnonzero(bad_x)
+
+
+def F(v):
+    return Fraction(float(v))
+
+
+def exact_infeasible(rows):
+    """Exact emptiness test of {x: a.x <= b for (a, b) in rows} for <= 3 rows
+    (Helly in the plane: a certificate needs at most three)."""
+    import oracle
+    ax = [r[0] for r in rows]
+    ay = [r[1] for r in rows]
+    b = [r[2] for r in rows]
+    st, _, _ = oracle.brute_force(ax, ay, b, 0.0, 0.0)
+    return st == INFEASIBLE
+
+
+def check_optimal_certificate(ax, ay, b, cx, cy, x, y, i, j, feas_tol=1e-9):
+    """x* feasible (max violation <= feas_tol * scale), lines i and j tight at
+    x*, and c in the cone of a_i, a_j (c = l_i a_i + l_j a_j, l >= 0).
+    Returns an error string or None."""
+    ax = np.asarray(ax, np.float64)
+    ay = np.asarray(ay, np.float64)
+    b = np.asarray(b, np.float64)
+    viol = ax * x + ay * y - b
+    scale = np.abs(ax * x) + np.abs(ay * y) + np.abs(b) + 1e-300
+    if np.any(viol > feas_tol * scale):
+        return f"infeasible x*: max rel violation {np.max(viol / scale):.3e}"
+    for k in (i, j):
+        if abs(viol[k]) > feas_tol * scale[k]:
+            return f"defining line {k} not tight ({viol[k]:.3e})"
+    det = ax[i] * ay[j] - ay[i] * ax[j]
+    if det == 0:
+        return "parallel defining pair"
+    li = (cx * ay[j] - cy * ax[j]) / det
+    lj = (ax[i] * cy - ay[i] * cx) / det
+    tol = 1e-12 * (abs(cx) + abs(cy) + 1.0)
+    if li < -tol or lj < -tol:
+        return f"c outside the normal cone (l = {li:.3e}, {lj:.3e})"
+    return None
+
+
+def check_unbounded_ray(ax, ay, b, cx, cy, l, dirn):
+    """Exact check of an unbounded certificate: the ray p0 + t d lies in P for
+    all large t (so P is non-empty and recedes along d) and
+    (c.d, -d1, -d2) >_lex 0.  Line l gives p0 = b_l a_l / |a_l|^2 and
+    d = dirn * (-a_l.y, a_l.x); l < 0 stands for the box-corner start
+    p0 = 0, d = (s_x, s_y)."""
+    if l < 0:
+        p0 = (Fraction(0), Fraction(0))
+        d = (Fraction(1 if cx > 0 else -1), Fraction(1 if cy > 0 else -1))
+    else:
+        alx, aly, bl = F(ax[l]), F(ay[l]), F(b[l])
+        n2 = alx * alx + aly * aly
+        p0 = (bl * alx / n2, bl * aly / n2)
+        d = (-aly * dirn, alx * dirn)
+    for p, q, r in zip(ax, ay, b):
+        p, q, r = F(p), F(q), F(r)
+        ad = p * d[0] + q * d[1]
+        if ad > 0 or (ad == 0 and p * p0[0] + q * p0[1] > r):
+            return "the ray leaves P"
+    key = (F(cx) * d[0] + F(cy) * d[1], -d[0], -d[1])
+    if not key > (0, 0, 0):
+        return "ray does not improve the objective"
+    return None

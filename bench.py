@@ -1,0 +1,149 @@
+"""Benchmark: batched 2D LP solving on one MI355X.
+
+One step = one solve of the whole synthetic workload (every LP of the batch,
+inputs resident in HBM).  Prints ONE JSON line with LPs/s of the batched
+solver (``value``), the plain one-LP-per-lane kernel on the same buffers,
+constraints/s, the HBM roofline of the dominant kernel (algorithmic bytes =
+12 B per half-plane + 28 B per LP, over its HIP-event-timed duration), and
+the FP64 oracle timed on the host cores as a baseline.
+
+    python bench.py [--steps K] [--warmup W] [--workload uniform|uneven|crowd|plain]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, public spec
+
+WORKLOADS = {
+    "uniform": "131,072 LPs x 256 half-planes (+4 box rows; 5% infeasible, 2% unbounded), FP32",
+    "uneven": "200,000 LPs, half-planes log-uniform in [8, 8192] (+box; 5% infeasible, 2% unbounded), FP32",
+    "crowd": "262,144 crowd-avoidance LPs, k~U[8,64] neighbours + 16 speed rows, FP32",
+    "plain": "1,024 LPs x 64 half-planes (+4 box rows), FP32",
+}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="uniform", choices=sorted(WORKLOADS))
+    ap.add_argument("--variant", default="auto")
+    ap.add_argument("--lanes", type=int, default=0)
+    ap.add_argument("--slots", type=int, default=0)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain-kernel comparison")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(json.dumps({"error": f"--gpus {args.gpus}: this build measures one GPU only; "
+                                   "LPs are independent, so N GPUs would each solve their own LP range"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1902_04995_amd as rgb
+    from paper_1902_04995_amd import gen
+
+    t0 = time.time()
+    bt = gen.make_config(args.workload, seed=0)
+    gen_s = time.time() - t0
+    print(f"[bench] generated {args.workload}: {bt.num_lps} LPs, {bt.num_constraints} rows in {gen_s:.1f}s",
+          file=sys.stderr, flush=True)
+    dev = rgb.DeviceBatch(bt, "cuda:0")
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    out = (torch.empty(bt.num_lps, dtype=torch.float32, device="cuda"),
+           torch.empty(bt.num_lps, dtype=torch.float32, device="cuda"),
+           torch.empty(bt.num_lps, dtype=torch.int32, device="cuda"))
+    alg_bytes = bt.algorithmic_bytes()
+
+    def run(variant, steps, warmup, **kw):
+        for _ in range(warmup):
+            dev.solve(variant=variant, out=out, stream=stream, **kw)
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        t_start = torch.cuda.Event(enable_timing=True)
+        t_end = torch.cuda.Event(enable_timing=True)
+        t_start.record(stream)
+        for a, b in ev:
+            a.record(stream)
+            dev.solve(variant=variant, out=out, stream=stream, **kw)
+            b.record(stream)
+        t_end.record(stream)
+        torch.cuda.synchronize()
+        total_ms = t_start.elapsed_time(t_end)
+        per = [a.elapsed_time(b) for a, b in ev]
+        return total_ms / steps, float(np.mean(per)), float(np.median(per)), per
+
+    kw = dict(lanes_per_lp=args.lanes, slots=args.slots)
+    ms_step, kern_ms, kern_med, per = run(args.variant, args.steps, args.warmup, **kw)
+    print(f"[bench] {args.variant}: {ms_step:.3f} ms/step, kernel mean {kern_ms:.3f} ms median {kern_med:.3f} ms",
+          file=sys.stderr, flush=True)
+    st = out[2].cpu().numpy()
+    status_counts = np.bincount(st, minlength=4).tolist()
+
+    plain = None
+    if not args.no_plain:
+        p_steps = max(2, min(args.steps, 5))
+        p_ms, p_kern, _, _ = run("plain", p_steps, 1)
+        plain = {"lps_per_s": bt.num_lps / (p_ms / 1e3), "ms_per_step": p_ms,
+                 "hbm_gbs": alg_bytes / (p_kern / 1e3) / 1e9, "steps": p_steps}
+        print(f"[bench] plain: {p_ms:.3f} ms/step", file=sys.stderr, flush=True)
+
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        threads = len(os.sched_getaffinity(0))
+        # bounded sample: the whole workload, solved once on every host core
+        t0 = time.perf_counter()
+        ref = oracle.solve(bt, threads=threads)
+        cpu_s = time.perf_counter() - t0
+        cpu = {"value": bt.num_lps / cpu_s, "unit": "LPs/s", "cores": int(ref["threads"]), "kind": "oracle",
+               "sample": f"all {bt.num_lps} LPs of the workload, one pass, FP64 serial Seidel per LP, "
+                         f"LPs split over {ref['threads']} threads ({cpu_s:.2f} s)"}
+        agree = int((ref["status"] == st).sum())
+        cpu["status_agree"] = f"{agree}/{bt.num_lps}"
+        print(f"[bench] oracle: {cpu_s:.2f}s on {ref['threads']} threads; status agree {agree}/{bt.num_lps}",
+              file=sys.stderr, flush=True)
+
+    achieved = alg_bytes / (kern_ms / 1e3) / 1e9
+    line = {
+        "metric": "LPs/sec + achieved HBM GB/s, batched vs plain kernel; p50/p99 served latency",
+        "value": bt.num_lps / (ms_step / 1e3),
+        "unit": "LPs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded generator, inputs resident in HBM)",
+        "config": {"workload": f"{args.workload}: {WORKLOADS[args.workload]}", "num_lps": bt.num_lps,
+                   "half_planes": bt.num_constraints, "variant": args.variant,
+                   "lanes_per_lp": args.lanes, "slots": args.slots},
+        "constraints_per_s": bt.num_constraints / (ms_step / 1e3),
+        "hbm_gbs": achieved,
+        "plain": plain,
+        "batched_over_plain": (bt.num_lps / (ms_step / 1e3)) / plain["lps_per_s"] if plain else None,
+        "status_counts": status_counts,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "solve", "algorithmic_bytes_per_launch": alg_bytes,
+                     "kernel_ms_mean": kern_ms, "kernel_ms_median": kern_med},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

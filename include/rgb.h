@@ -1,0 +1,130 @@
+/*
+ * rgb.h - C ABI of the batched two-dimensional LP solver for MI355X (gfx950).
+ *
+ * Each LP k of a batch is (Eq. (1)-(2), Sec. 2.1 of Charlton, Maddock and
+ * Richmond, "Two-Dimensional Batch Linear Programming on the GPU"):
+ *
+ *     maximize  cx[k]*x + cy[k]*y
+ *     subject to ax[i]*x + ay[i]*y <= b[i]   for offsets[k] <= i < offsets[k+1]
+ *
+ * Solved with Seidel's randomized incremental method (Sec. 2.1) as a batch on
+ * the GPU (Sec. 3): constraints are taken in the order given, so the caller
+ * supplies them in random order (Sec. 2.1 needs a random order for the
+ * expected O(m) cost; the solver itself never shuffles).
+ *
+ * Result (per LP): x* is the lexicographically smallest maximiser (among the
+ * optimal points the one with the smallest x, then the smallest y); the
+ * paper's bounding rows x <= M, x >= -M (Sec. 2.1) are taken with M -> infinity.
+ *   RGB_OPTIMAL    x*, y* written
+ *   RGB_INFEASIBLE no point satisfies every row (x, y = NaN)
+ *   RGB_UNBOUNDED  feasible, no lexicographic optimum (x, y = NaN)
+ *   RGB_INVALID    a non-finite ax/ay/b/cx/cy in the LP, or malformed offsets
+ *                  for this LP (x, y = NaN)
+ * A row with ax = ay = 0 means 0 <= b: it empties the LP if b < 0 and is
+ * ignored otherwise.  An LP with no rows is RGB_UNBOUNDED.
+ *
+ * Memory: every buffer argument of the solve calls is DEVICE memory of the
+ * context's device, owned by the caller, and must stay valid until the work
+ * on `stream` completes.  Layout is CSR-offset SoA:
+ *   offsets  int64[num_lps + 1], offsets[0] = 0, non-decreasing,
+ *            offsets[num_lps] = num_constraints
+ *   ax, ay, b float32[num_constraints]   (rows of LP k are contiguous)
+ *   cx, cy    float32[num_lps]
+ *   x_out, y_out float32[num_lps], status_out int32[num_lps] (rgb_status_t)
+ * Rows are read only inside [0, num_constraints): an LP whose offsets fall
+ * outside, decrease, or span more than 2^30 rows gets RGB_INVALID instead of
+ * being read.
+ *
+ * Errors: calls return rgb_err_t synchronously for argument errors and never
+ * throw across the ABI.  Launch failures return RGB_ERR_DEVICE; a fault
+ * during asynchronous execution surfaces at the caller's next
+ * synchronisation.  rgb_ctx_last_error() gives a message for the last error
+ * on that context.  A context is not thread-safe: use one per host thread or
+ * lock around it.
+ */
+#ifndef RGB_H_
+#define RGB_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    RGB_OPTIMAL = 0,
+    RGB_INFEASIBLE = 1,
+    RGB_UNBOUNDED = 2,
+    RGB_INVALID = 3
+} rgb_status_t;
+
+typedef enum {
+    RGB_OK = 0,
+    RGB_ERR_INVALID_ARG = -1,
+    RGB_ERR_OOM = -2,
+    RGB_ERR_DEVICE = -3,
+    RGB_ERR_BUSY = -4,
+    RGB_ERR_TOO_LARGE = -5,
+    RGB_ERR_NOT_FOUND = -6
+} rgb_err_t;
+
+/* Kernel families (Sec. 3).  PLAIN is the one-LP-per-lane form the paper
+ * calls NaiveRGB; BATCHED gives each LP a group of lanes that hold its rows
+ * in registers and split every 1D LP's work units among themselves;
+ * PERSISTENT bins LPs by size and runs one persistent launch that takes
+ * work from a device queue, largest LPs first.  AUTO = PERSISTENT. */
+typedef enum {
+    RGB_VARIANT_AUTO = 0,
+    RGB_VARIANT_PLAIN = 1,
+    RGB_VARIANT_BATCHED = 2,
+    RGB_VARIANT_PERSISTENT = 3
+} rgb_variant_t;
+
+typedef struct rgb_ctx rgb_ctx_t;
+
+/* Optional per-call settings; pass NULL for defaults.  Zero means "default"
+ * for every numeric field. */
+typedef struct {
+    int32_t variant;        /* rgb_variant_t */
+    int32_t lanes_per_lp;   /* BATCHED: lanes per LP, one of 4, 8, 16, 32, 64 */
+    int32_t slots;          /* BATCHED: rows held in registers per lane (power of 2, <= 32);
+                               rows beyond lanes_per_lp*slots are re-read from memory */
+    int32_t chunk;          /* PERSISTENT: queue entries taken per pop */
+    int32_t grid;           /* PERSISTENT: workgroups launched */
+    int32_t reserved;
+    int32_t* n_1dlp_out;    /* optional device int32[num_lps]: 1D LPs solved per LP */
+} rgb_solve_opts_t;
+
+/* Version string of the library. */
+const char* rgb_version(void);
+
+/* Create a context on HIP device `device` (the caller's current device is
+ * left unchanged).  *out receives the context.  Errors: INVALID_ARG (bad
+ * device or NULL out), DEVICE. */
+rgb_err_t rgb_ctx_create(int device, rgb_ctx_t** out);
+
+/* Free the context and its workspace.  Waits for no stream: the caller
+ * synchronises the streams it used first.  NULL is a no-op. */
+rgb_err_t rgb_ctx_destroy(rgb_ctx_t* ctx);
+
+/* Message for the last error on ctx (empty if none; static text if ctx is NULL). */
+const char* rgb_ctx_last_error(const rgb_ctx_t* ctx);
+
+/* Solve num_lps LPs (Eq. (1)-(2)); enqueues work on `stream` (a hipStream_t,
+ * NULL = the null stream) and returns without waiting.  Layout, ownership and
+ * per-LP status as described at the top of this file.  num_lps = 0 is a
+ * no-op.  Workspace is taken from the context and grown with hipMalloc when
+ * needed (never during stream capture: INVALID_ARG then).  Errors:
+ * INVALID_ARG (NULL pointer with num_lps > 0, negative counts, bad option),
+ * OOM, DEVICE. */
+rgb_err_t rgb_solve_batch(rgb_ctx_t* ctx, int64_t num_lps, int64_t num_constraints,
+                          const int64_t* offsets, const float* ax, const float* ay, const float* b,
+                          const float* cx, const float* cy, float* x_out, float* y_out,
+                          int32_t* status_out, const rgb_solve_opts_t* opts, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RGB_H_ */

@@ -1,0 +1,178 @@
+"""Batched two-dimensional LP solver for MI355X (gfx950).
+
+Thin Python binding over the C ABI in ``include/rgb.h`` (``librgb.so``,
+built in-tree by ``build.py``).  Every step of the solve runs in the HIP
+kernels; this module only marshals arguments.  PyTorch provides device
+memory and streams.  There is no CPU fallback: if the library is missing,
+every call raises.
+
+    import torch, paper_1902_04995_amd as rgb
+    x, y, status = rgb.solve_batch(offsets, ax, ay, b, cx, cy)   # CUDA tensors
+
+Statuses: OPTIMAL=0, INFEASIBLE=1, UNBOUNDED=2, INVALID=3.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+OPTIMAL, INFEASIBLE, UNBOUNDED, INVALID = 0, 1, 2, 3
+VARIANTS = {"auto": 0, "plain": 1, "batched": 2, "persistent": 3}
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librgb.so")
+_lib = None
+_lock = threading.Lock()
+_ctx_cache = {}
+
+
+class RgbError(RuntimeError):
+    pass
+
+
+class _SolveOpts(ctypes.Structure):
+    _fields_ = [("variant", ctypes.c_int32), ("lanes_per_lp", ctypes.c_int32), ("slots", ctypes.c_int32),
+                ("chunk", ctypes.c_int32), ("grid", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("n_1dlp_out", ctypes.c_void_p)]
+
+
+def lib():
+    """Load librgb.so (after torch, so both use one HIP runtime)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        import torch  # noqa: F401  (binds the process to torch's HIP runtime first)
+        if not os.path.exists(LIB_PATH):
+            raise RgbError(f"{LIB_PATH} is missing: run paper_1902_04995_amd/build.py (or __graft_entry__.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        P, I64, I32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+        L.rgb_version.restype = ctypes.c_char_p
+        L.rgb_ctx_create.argtypes = [ctypes.c_int, ctypes.POINTER(P)]
+        L.rgb_ctx_create.restype = I32
+        L.rgb_ctx_destroy.argtypes = [P]
+        L.rgb_ctx_destroy.restype = I32
+        L.rgb_ctx_last_error.argtypes = [P]
+        L.rgb_ctx_last_error.restype = ctypes.c_char_p
+        L.rgb_solve_batch.argtypes = [P, I64, I64] + [P] * 9 + [ctypes.POINTER(_SolveOpts), P]
+        L.rgb_solve_batch.restype = I32
+        _lib = L
+    return _lib
+
+
+class Context:
+    """Owns an rgb_ctx_t on one device."""
+
+    def __init__(self, device: int = 0):
+        L = lib()
+        h = ctypes.c_void_p()
+        rc = L.rgb_ctx_create(int(device), ctypes.byref(h))
+        if rc != 0:
+            raise RgbError(f"rgb_ctx_create({device}) failed: {rc}")
+        self.handle = h
+        self.device = int(device)
+
+    def check(self, rc: int, what: str):
+        if rc != 0:
+            msg = lib().rgb_ctx_last_error(self.handle).decode()
+            raise RgbError(f"{what} failed ({rc}): {msg}")
+
+    def close(self):
+        if self.handle:
+            lib().rgb_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def context(device: int = 0) -> Context:
+    ctx = _ctx_cache.get(device)
+    if ctx is None:
+        ctx = _ctx_cache[device] = Context(device)
+    return ctx
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _check_tensor(t, name, dtype, device):
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if t.device != device:
+        raise ValueError(f"{name} is on {t.device}, expected {device}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def make_opts(variant="auto", lanes_per_lp=0, slots=0, chunk=0, grid=0, n_1dlp=None) -> _SolveOpts:
+    o = _SolveOpts()
+    o.variant = VARIANTS[variant] if isinstance(variant, str) else int(variant)
+    o.lanes_per_lp = int(lanes_per_lp)
+    o.slots = int(slots)
+    o.chunk = int(chunk)
+    o.grid = int(grid)
+    o.n_1dlp_out = n_1dlp.data_ptr() if n_1dlp is not None else None
+    return o
+
+
+def solve_batch(offsets, ax, ay, b, cx, cy, *, variant="auto", lanes_per_lp=0, slots=0, chunk=0, grid=0,
+                want_n_1dlp=False, out=None, stream=None, ctx: Context | None = None):
+    """Solve a CSR-offset SoA batch held in CUDA tensors (offsets int64[B+1];
+    ax, ay, b float32[N]; cx, cy float32[B]).  Enqueues on ``stream`` (default:
+    torch's current stream) and returns (x, y, status[, n_1dlp]) tensors that
+    are valid once that stream has run the work."""
+    import torch
+    dev = offsets.device
+    if dev.type != "cuda":
+        raise ValueError("solve_batch needs CUDA tensors")
+    _check_tensor(offsets, "offsets", torch.int64, dev)
+    for name, t in (("ax", ax), ("ay", ay), ("b", b), ("cx", cx), ("cy", cy)):
+        _check_tensor(t, name, torch.float32, dev)
+    B = offsets.numel() - 1
+    N = ax.numel()
+    if B < 0 or ay.numel() != N or b.numel() != N or cx.numel() != B or cy.numel() != B:
+        raise ValueError("inconsistent batch shapes")
+    if out is None:
+        x = torch.empty(B, dtype=torch.float32, device=dev)
+        y = torch.empty(B, dtype=torch.float32, device=dev)
+        st = torch.empty(B, dtype=torch.int32, device=dev)
+    else:
+        x, y, st = out
+    n1d = torch.empty(B, dtype=torch.int32, device=dev) if want_n_1dlp else None
+    ctx = ctx or context(dev.index or 0)
+    if stream is None:
+        stream = torch.cuda.current_stream(dev)
+    opts = make_opts(variant, lanes_per_lp, slots, chunk, grid, n1d)
+    rc = lib().rgb_solve_batch(ctx.handle, B, N, _ptr(offsets), _ptr(ax), _ptr(ay), _ptr(b), _ptr(cx), _ptr(cy),
+                               _ptr(x), _ptr(y), _ptr(st), ctypes.byref(opts), ctypes.c_void_p(stream.cuda_stream))
+    ctx.check(rc, "rgb_solve_batch")
+    if want_n_1dlp:
+        return x, y, st, n1d
+    return x, y, st
+
+
+class DeviceBatch:
+    """A gen.Batch copied to device memory."""
+
+    def __init__(self, batch, device="cuda"):
+        import torch
+        t = lambda a: torch.from_numpy(a).to(device)
+        self.offsets = t(batch.offsets)
+        self.ax, self.ay, self.b = t(batch.ax), t(batch.ay), t(batch.b)
+        self.cx, self.cy = t(batch.cx), t(batch.cy)
+        self.num_lps = batch.num_lps
+        self.num_constraints = batch.num_constraints
+
+    def solve(self, **kw):
+        return solve_batch(self.offsets, self.ax, self.ay, self.b, self.cx, self.cy, **kw)

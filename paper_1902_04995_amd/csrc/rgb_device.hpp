@@ -1,0 +1,300 @@
+// Device-side numerics of the batched 2D LP solver (gfx950).
+//
+// One LP: maximize c.x subject to a_i.x <= b_i (Eq. (1)-(2)), solved with
+// Seidel's incremental method (Sec. 2.1).  The bounding rows x <= M, x >= -M
+// of Sec. 2.1 are symbolic (M -> infinity), so a state is
+//   kCorner  the box corner M*(s_x, s_y): a ray from the origin,
+//   kRay     a ray p0 + t*q (t -> infinity) along line l,
+//   kPoint   the vertex of lines l and h, kept as the FP32 point p,
+//   kDead    infeasible or invalid (final).
+// A row that the state violates starts a 1D LP on its line over the earlier
+// rows (Eq. (3)-(4)): each earlier row is one work unit (Sec. 3) giving a
+// left or right bound on the line.
+//
+// Arithmetic is FP32 with three guards that keep every status decision
+// equal to the exact one:
+//   * signs of 2x2 determinants of inputs (which side a row bounds, whether
+//     two rows are parallel, the direction c prefers along a line, ray
+//     tests) use Kahan's FMA determinant, whose relative error is below
+//     2 ulps, so the sign and an exact zero are always right;
+//   * the parallel case (Sec. 2.1: the row either leaves the line whole or
+//     empties it) and parallel ray tests are decided in FP64, where
+//     products of FP32 inputs are exact;
+//   * when u_left and u_right (Eq. (3)-(4)) are within FP32 noise of each
+//     other, infeasibility is re-decided in FP64 from the two bounding rows.
+// x* is recomputed at the end by Cramer's rule from the defining pair, with
+// Kahan determinants (a few ulps per component).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rgb {
+
+constexpr int kOptimal = 0;
+constexpr int kInfeasible = 1;
+constexpr int kUnbounded = 2;
+constexpr int kInvalid = 3;
+
+constexpr int kCorner = 0;
+constexpr int kRay = 1;
+constexpr int kPoint = 2;
+constexpr int kDead = 3;
+
+constexpr int kNoIdx = 0x7fffffff;
+constexpr int64_t kMaxRows = int64_t(1) << 30;
+
+// Near-tie threshold for u_left vs u_right, relative to the bound magnitudes.
+constexpr float kTieRel = 1.0e-4f;
+
+struct Problem {
+    const int64_t* offsets;
+    const float* ax;
+    const float* ay;
+    const float* b;
+    const float* cx;
+    const float* cy;
+    float* x_out;
+    float* y_out;
+    int32_t* status;
+    int32_t* n1d;          // optional
+    const int32_t* order;  // optional: queue position -> LP id
+    int64_t num_lps;
+    int64_t num_constraints;
+};
+
+// ax*px + ay*py with a sign that is always right and an exact zero
+// (Kahan's FMA-based 2x2 determinant).
+__device__ __forceinline__ float dot2_exact(float ax, float ay, float px, float py) {
+    float w = ay * py;
+    float e = __builtin_fmaf(ay, py, -w);
+    float f = __builtin_fmaf(ax, px, w);
+    return f + e;
+}
+
+struct LpState {
+    int kind;
+    int dead_status;
+    float px, py, qx, qy;
+    float lx, ly, lb;  // line l of a kRay / kPoint state
+    int l, h;
+};
+
+struct Line {
+    float lx, ly, lb;   // a_l, b_l
+    float ux, uy;       // direction u = (-a_l.y, a_l.x)
+    float p0x, p0y;     // b_l a_l / |a_l|^2
+    float pscale;       // |p0| / |u|: the scale of positions along the line
+    double n2;          // |a_l|^2 in FP64
+};
+
+struct Bounds {
+    float hi, lo;       // u_right (min over right bounds), u_left (max over left bounds)
+    int hi_idx, lo_idx;
+    bool par_inf;       // a parallel earlier row empties the line
+};
+
+__device__ __forceinline__ void init_state(LpState& st, float cx, float cy) {
+    st.kind = kCorner;
+    st.dead_status = kOptimal;
+    st.px = 0.0f;
+    st.py = 0.0f;
+    st.qx = cx > 0.0f ? 1.0f : -1.0f;
+    st.qy = cy > 0.0f ? 1.0f : -1.0f;
+    st.lx = st.ly = st.lb = 0.0f;
+    st.l = -1;
+    st.h = -1;
+}
+
+// Does row (ax, ay, b) cut off the current state?  (Sec. 2.1, outcome (2).)
+__device__ __forceinline__ bool row_violates(float ax, float ay, float b, const LpState& st) {
+    if (st.kind == kPoint) return __builtin_fmaf(ax, st.px, __builtin_fmaf(ay, st.py, -b)) > 0.0f;
+    float t = dot2_exact(ax, ay, st.qx, st.qy);
+    if (t != 0.0f) return t > 0.0f;
+    if (st.kind == kCorner) return b < 0.0f;
+    // row parallel to the ray's line: compare a.p0 with b exactly,
+    // a.p0 = b_l (a.a_l) / |a_l|^2
+    double l2 = (double)st.lx * st.lx + (double)st.ly * st.ly;
+    double al = (double)ax * st.lx + (double)ay * st.ly;
+    return (double)st.lb * al > (double)b * l2;
+}
+
+__device__ __forceinline__ void make_line(Line& L, float lx, float ly, float lb) {
+    L.lx = lx;
+    L.ly = ly;
+    L.lb = lb;
+    L.ux = -ly;
+    L.uy = lx;
+    float n2 = __builtin_fmaf(lx, lx, ly * ly);
+    float k = lb / n2;
+    L.p0x = k * lx;
+    L.p0y = k * ly;
+    L.pscale = __builtin_fabsf(k);
+    L.n2 = (double)lx * lx + (double)ly * ly;
+}
+
+__device__ __forceinline__ void init_bounds(Bounds& B) {
+    B.hi = __builtin_huge_valf();
+    B.lo = -__builtin_huge_valf();
+    B.hi_idx = kNoIdx;
+    B.lo_idx = kNoIdx;
+    B.par_inf = false;
+}
+
+// One work unit: earlier row (ax, ay, b) with index idx bounds line L
+// (Eq. (3)-(4)).  Position along u: sigma = (b - a.p0) / (a.u).
+__device__ __forceinline__ void work_unit(float ax, float ay, float b, int idx, const Line& L, Bounds& B) {
+    float D = dot2_exact(ax, ay, L.ux, L.uy);
+    float r = __builtin_fmaf(-ax, L.p0x, __builtin_fmaf(-ay, L.p0y, b));
+    float sig = r * __builtin_amdgcn_rcpf(D);
+    if (D > 0.0f) {
+        if (sig < B.hi) {
+            B.hi = sig;
+            B.hi_idx = idx;
+        }
+    } else if (D < 0.0f) {
+        if (sig > B.lo) {
+            B.lo = sig;
+            B.lo_idx = idx;
+        }
+    } else {
+        // parallel row (or zero normal): the line lies inside it iff
+        // N = b |a_l|^2 - b_l (a.a_l) >= 0; exact in FP64 for FP32 inputs
+        double N = (double)b * L.n2 - (double)L.lb * ((double)ax * L.lx + (double)ay * L.ly);
+        if (N < 0.0) B.par_inf = true;
+    }
+}
+
+// Merge two partial results; ties keep the smaller row index.
+__device__ __forceinline__ void merge_bounds(Bounds& B, float ohi, int ohi_idx, float olo, int olo_idx) {
+    if (ohi < B.hi || (ohi == B.hi && ohi_idx < B.hi_idx)) {
+        B.hi = ohi;
+        B.hi_idx = ohi_idx;
+    }
+    if (olo > B.lo || (olo == B.lo && olo_idx < B.lo_idx)) {
+        B.lo = olo;
+        B.lo_idx = olo_idx;
+    }
+}
+
+// Exact-in-FP64 re-decision of u_left > u_right from the two bounding rows.
+// With D_h = a_l x a_h and N_h = b_h |a_l|^2 - b_l (a_l.a_h), a bound sits at
+// N_h / D_h along u (scaled by |a_l|^2); lo > hi iff N_lo D_hi < N_hi D_lo.
+__device__ __forceinline__ bool exact_lo_gt_hi(const Line& L, float lox, float loy, float lob, float hix,
+                                               float hiy, float hib) {
+    double lx = L.lx, ly = L.ly, lb = L.lb;
+    double Dlo = lx * (double)loy - ly * (double)lox;
+    double Dhi = lx * (double)hiy - ly * (double)hix;
+    double Nlo = (double)lob * L.n2 - lb * (lx * (double)lox + ly * (double)loy);
+    double Nhi = (double)hib * L.n2 - lb * (lx * (double)hix + ly * (double)hiy);
+    return Nlo * Dhi < Nhi * Dlo;
+}
+
+// Apply the outcome of a 1D LP on line L (row index v) to the state.
+// rows_* point at the LP's first row (global memory) for the rare exact re-check.
+__device__ __forceinline__ void apply_1dlp(LpState& st, int v, const Line& L, const Bounds& B, float cx, float cy,
+                                           const float* rax, const float* ray, const float* rb) {
+    if (B.par_inf) {
+        st.kind = kDead;
+        st.dead_status = kInfeasible;
+        return;
+    }
+    if (B.hi_idx != kNoIdx && B.lo_idx != kNoIdx) {
+        bool inf = B.lo > B.hi;
+        float scale = __builtin_fabsf(B.hi) + __builtin_fabsf(B.lo) + L.pscale;
+        if (__builtin_fabsf(B.hi - B.lo) <= kTieRel * scale) {
+            inf = exact_lo_gt_hi(L, rax[B.lo_idx], ray[B.lo_idx], rb[B.lo_idx], rax[B.hi_idx], ray[B.hi_idx],
+                                 rb[B.hi_idx]);
+        }
+        if (inf) {
+            st.kind = kDead;
+            st.dead_status = kInfeasible;
+            return;
+        }
+    }
+    // direction c prefers along u: first non-zero of (c.u, -u.x, -u.y)
+    float cu = dot2_exact(cx, cy, L.ux, L.uy);
+    bool up;
+    if (cu != 0.0f) up = cu > 0.0f;
+    else if (L.ly != 0.0f) up = L.ly > 0.0f;
+    else up = L.lx < 0.0f;
+    int pick = up ? B.hi_idx : B.lo_idx;
+    float sig = up ? B.hi : B.lo;
+    st.l = v;
+    st.lx = L.lx;
+    st.ly = L.ly;
+    st.lb = L.lb;
+    if (pick == kNoIdx) {
+        st.kind = kRay;
+        st.px = L.p0x;
+        st.py = L.p0y;
+        st.qx = up ? L.ux : -L.ux;
+        st.qy = up ? L.uy : -L.uy;
+    } else {
+        st.kind = kPoint;
+        st.h = pick;
+        st.px = __builtin_fmaf(sig, L.ux, L.p0x);
+        st.py = __builtin_fmaf(sig, L.uy, L.p0y);
+        st.qx = 0.0f;
+        st.qy = 0.0f;
+    }
+}
+
+__device__ __forceinline__ bool row_less(float ax1, float ay1, float b1, float ax2, float ay2, float b2) {
+    if (ax1 != ax2) return ax1 < ax2;
+    if (ay1 != ay2) return ay1 < ay2;
+    return b1 < b2;
+}
+
+// Final x*, status for one LP and the output store.
+__device__ __forceinline__ void finish_lp(const Problem& P, int64_t lp, int64_t start, const LpState& st,
+                                          int n1d) {
+    float nan = __builtin_nanf("");
+    float x = nan, y = nan;
+    int status;
+    if (st.kind == kDead) {
+        status = st.dead_status;
+    } else if (st.kind == kPoint) {
+        float a1x = P.ax[start + st.l], a1y = P.ay[start + st.l], b1 = P.b[start + st.l];
+        float a2x = P.ax[start + st.h], a2y = P.ay[start + st.h], b2 = P.b[start + st.h];
+        if (row_less(a2x, a2y, b2, a1x, a1y, b1)) {
+            float t;
+            t = a1x; a1x = a2x; a2x = t;
+            t = a1y; a1y = a2y; a2y = t;
+            t = b1; b1 = b2; b2 = t;
+        }
+        // Cramer: W = a1 x a2, X = b1 a2.y - b2 a1.y, Y = a1.x b2 - a2.x b1
+        float W = dot2_exact(a1x, -a1y, a2y, a2x);
+        float X = dot2_exact(b1, -b2, a2y, a1y);
+        float Y = dot2_exact(a1x, -a2x, b2, b1);
+        x = X / W;
+        y = Y / W;
+        status = kOptimal;
+    } else {
+        status = kUnbounded;
+    }
+    P.x_out[lp] = x;
+    P.y_out[lp] = y;
+    P.status[lp] = status;
+    if (P.n1d) P.n1d[lp] = n1d;
+}
+
+// Row range of LP lp, checked against the row arrays.  Returns false (and
+// the LP is INVALID) when the offsets are out of range, decreasing or huge.
+__device__ __forceinline__ bool lp_range(const Problem& P, int64_t lp, int64_t& start, int& m) {
+    int64_t s = P.offsets[lp], e = P.offsets[lp + 1];
+    if (s < 0 || e < s || e > P.num_constraints || e - s > kMaxRows) {
+        start = 0;
+        m = 0;
+        return false;
+    }
+    start = s;
+    m = (int)(e - s);
+    return true;
+}
+
+__device__ __forceinline__ bool finite3(float a, float b, float c) {
+    return __builtin_isfinite(a) && __builtin_isfinite(b) && __builtin_isfinite(c);
+}
+
+}  // namespace rgb

@@ -70,8 +70,8 @@ typedef enum {
 } rgb_err_t;
 
 /* Kernel families (Sec. 3).  PLAIN is the one-LP-per-lane form the paper
- * calls NaiveRGB; BATCHED gives each LP a group of lanes that hold its rows
- * in registers and split every 1D LP's work units among themselves;
+ * calls NaiveRGB; BATCHED gives each LP a group of lanes that scan its rows
+ * and split every 1D LP's work units among themselves;
  * PERSISTENT bins LPs by size and runs one persistent launch that takes
  * work from a device queue, largest LPs first.  AUTO = PERSISTENT. */
 typedef enum {
@@ -88,8 +88,7 @@ typedef struct rgb_ctx rgb_ctx_t;
 typedef struct {
     int32_t variant;        /* rgb_variant_t */
     int32_t lanes_per_lp;   /* BATCHED: lanes per LP, one of 4, 8, 16, 32, 64 */
-    int32_t slots;          /* BATCHED: rows held in registers per lane (power of 2, <= 32);
-                               rows beyond lanes_per_lp*slots are re-read from memory */
+    int32_t slots;          /* reserved, must be 0 */
     int32_t chunk;          /* PERSISTENT: queue entries taken per pop */
     int32_t grid;           /* PERSISTENT: workgroups launched */
     int32_t reserved;

@@ -41,8 +41,7 @@ struct DeviceGuard {
     }
 };
 
-constexpr int kDefaultLanes = 64;
-constexpr int kDefaultSlots = 5;
+constexpr int kDefaultLanes = 16;
 
 }  // namespace
 
@@ -117,10 +116,9 @@ rgb_err_t rgb_solve_batch(rgb_ctx_t* ctx, int64_t num_lps, int64_t num_constrain
         e = rgb::launch_plain(P, st);
     } else {
         int g = o.lanes_per_lp ? o.lanes_per_lp : kDefaultLanes;
-        int s = o.slots ? o.slots : kDefaultSlots;
-        if (!rgb::group_supported(g, s))
-            return fail(ctx, RGB_ERR_INVALID_ARG, "lanes_per_lp=%d slots=%d is not a compiled shape", g, s);
-        e = rgb::launch_group(P, g, s, st);
+        if (!rgb::group_supported(g))
+            return fail(ctx, RGB_ERR_INVALID_ARG, "lanes_per_lp=%d is not one of 4, 8, 16, 32, 64", g);
+        e = rgb::launch_group(P, g, st);
     }
     if (e != hipSuccess) return fail(ctx, RGB_ERR_DEVICE, "launch failed: %s", hipGetErrorString(e));
     return RGB_OK;

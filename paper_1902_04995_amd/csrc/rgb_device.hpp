@@ -77,7 +77,9 @@ struct LpState {
     int dead_status;
     float px, py, qx, qy;
     float lx, ly, lb;  // line l of a kRay / kPoint state
-    int l, h;
+    int l;             // row index of line l
+    float sig;         // kPoint: position of the vertex along u_l
+    bool up;           // kPoint: the vertex is u_right (true) or u_left (false) of line l
 };
 
 struct Line {
@@ -85,13 +87,6 @@ struct Line {
     float ux, uy;       // direction u = (-a_l.y, a_l.x)
     float p0x, p0y;     // b_l a_l / |a_l|^2
     float pscale;       // |p0| / |u|: the scale of positions along the line
-    double n2;          // |a_l|^2 in FP64
-};
-
-struct Bounds {
-    float hi, lo;       // u_right (min over right bounds), u_left (max over left bounds)
-    int hi_idx, lo_idx;
-    bool par_inf;       // a parallel earlier row empties the line
 };
 
 __device__ __forceinline__ void init_state(LpState& st, float cx, float cy) {
@@ -103,16 +98,22 @@ __device__ __forceinline__ void init_state(LpState& st, float cx, float cy) {
     st.qy = cy > 0.0f ? 1.0f : -1.0f;
     st.lx = st.ly = st.lb = 0.0f;
     st.l = -1;
-    st.h = -1;
+    st.sig = 0.0f;
+    st.up = false;
 }
 
-// Does row (ax, ay, b) cut off the current state?  (Sec. 2.1, outcome (2).)
+// Does row (ax, ay, b) cut off a kPoint state?  (Sec. 2.1, outcome (2).)
+__device__ __forceinline__ bool point_violated(float ax, float ay, float b, float px, float py) {
+    return __builtin_fmaf(ax, px, __builtin_fmaf(ay, py, -b)) > 0.0f;
+}
+
+// Same test for any live state.
 __device__ __forceinline__ bool row_violates(float ax, float ay, float b, const LpState& st) {
-    if (st.kind == kPoint) return __builtin_fmaf(ax, st.px, __builtin_fmaf(ay, st.py, -b)) > 0.0f;
+    if (st.kind == kPoint) return point_violated(ax, ay, b, st.px, st.py);
     float t = dot2_exact(ax, ay, st.qx, st.qy);
     if (t != 0.0f) return t > 0.0f;
     if (st.kind == kCorner) return b < 0.0f;
-    // row parallel to the ray's line: compare a.p0 with b exactly,
+    // row parallel to the ray's line: compare a.p0 with b in FP64,
     // a.p0 = b_l (a.a_l) / |a_l|^2
     double l2 = (double)st.lx * st.lx + (double)st.ly * st.ly;
     double al = (double)ax * st.lx + (double)ay * st.ly;
@@ -125,56 +126,41 @@ __device__ __forceinline__ void make_line(Line& L, float lx, float ly, float lb)
     L.lb = lb;
     L.ux = -ly;
     L.uy = lx;
-    float n2 = __builtin_fmaf(lx, lx, ly * ly);
-    float k = lb / n2;
+    float k = lb / __builtin_fmaf(lx, lx, ly * ly);
     L.p0x = k * lx;
     L.p0y = k * ly;
     L.pscale = __builtin_fabsf(k);
-    L.n2 = (double)lx * lx + (double)ly * ly;
 }
 
-__device__ __forceinline__ void init_bounds(Bounds& B) {
-    B.hi = __builtin_huge_valf();
-    B.lo = -__builtin_huge_valf();
-    B.hi_idx = kNoIdx;
-    B.lo_idx = kNoIdx;
-    B.par_inf = false;
-}
-
-// One work unit: earlier row (ax, ay, b) with index idx bounds line L
-// (Eq. (3)-(4)).  Position along u: sigma = (b - a.p0) / (a.u).
-__device__ __forceinline__ void work_unit(float ax, float ay, float b, int idx, const Line& L, Bounds& B) {
-    float D = dot2_exact(ax, ay, L.ux, L.uy);
+// Position along u of the intersection of line L with row (ax, ay, b), and
+// the side it bounds: D = a.u > 0 bounds from the right (an upper bound on
+// the position, Eq. (4)), D < 0 from the left (Eq. (3)), D = 0 is parallel.
+// sigma = (b - a.p0) / D.  Every kernel uses this one function, so the same
+// row always yields the same bits.
+__device__ __forceinline__ float wu_sigma(float ax, float ay, float b, const Line& L, float& D) {
+    D = dot2_exact(ax, ay, L.ux, L.uy);
     float r = __builtin_fmaf(-ax, L.p0x, __builtin_fmaf(-ay, L.p0y, b));
-    float sig = r * __builtin_amdgcn_rcpf(D);
-    if (D > 0.0f) {
-        if (sig < B.hi) {
-            B.hi = sig;
-            B.hi_idx = idx;
-        }
-    } else if (D < 0.0f) {
-        if (sig > B.lo) {
-            B.lo = sig;
-            B.lo_idx = idx;
-        }
-    } else {
-        // parallel row (or zero normal): the line lies inside it iff
-        // N = b |a_l|^2 - b_l (a.a_l) >= 0; exact in FP64 for FP32 inputs
-        double N = (double)b * L.n2 - (double)L.lb * ((double)ax * L.lx + (double)ay * L.ly);
-        if (N < 0.0) B.par_inf = true;
-    }
+    return r * __builtin_amdgcn_rcpf(D);
 }
 
-// Merge two partial results; ties keep the smaller row index.
-__device__ __forceinline__ void merge_bounds(Bounds& B, float ohi, int ohi_idx, float olo, int olo_idx) {
-    if (ohi < B.hi || (ohi == B.hi && ohi_idx < B.hi_idx)) {
-        B.hi = ohi;
-        B.hi_idx = ohi_idx;
-    }
-    if (olo > B.lo || (olo == B.lo && olo_idx < B.lo_idx)) {
-        B.lo = olo;
-        B.lo_idx = olo_idx;
-    }
+// Parallel row (or zero normal): does it empty line L?  The line lies inside
+// the row iff N = b |a_l|^2 - b_l (a.a_l) >= 0; decided in FP64, where the
+// products of FP32 inputs are exact.
+__device__ __forceinline__ bool parallel_empties(float ax, float ay, float b, const Line& L) {
+    double n2 = (double)L.lx * L.lx + (double)L.ly * L.ly;
+    double N = (double)b * n2 - (double)L.lb * ((double)ax * L.lx + (double)ay * L.ly);
+    return N < 0.0;
+}
+
+// One work unit (Sec. 3): fold row (ax, ay, b) into the bounds on line L.
+// hi = min over right bounds (u_right), lo = max over left bounds (u_left).
+__device__ __forceinline__ void work_unit(float ax, float ay, float b, const Line& L, float& hi, float& lo,
+                                          bool& par_inf) {
+    float D;
+    float sig = wu_sigma(ax, ay, b, L, D);
+    hi = __builtin_fminf(hi, D > 0.0f ? sig : __builtin_huge_valf());
+    lo = __builtin_fmaxf(lo, D < 0.0f ? sig : -__builtin_huge_valf());
+    if (__builtin_expect(D == 0.0f, 0)) par_inf |= parallel_empties(ax, ay, b, L);
 }
 
 // Exact-in-FP64 re-decision of u_left > u_right from the two bounding rows.
@@ -183,48 +169,37 @@ __device__ __forceinline__ void merge_bounds(Bounds& B, float ohi, int ohi_idx, 
 __device__ __forceinline__ bool exact_lo_gt_hi(const Line& L, float lox, float loy, float lob, float hix,
                                                float hiy, float hib) {
     double lx = L.lx, ly = L.ly, lb = L.lb;
+    double n2 = lx * lx + ly * ly;
     double Dlo = lx * (double)loy - ly * (double)lox;
     double Dhi = lx * (double)hiy - ly * (double)hix;
-    double Nlo = (double)lob * L.n2 - lb * (lx * (double)lox + ly * (double)loy);
-    double Nhi = (double)hib * L.n2 - lb * (lx * (double)hix + ly * (double)hiy);
+    double Nlo = (double)lob * n2 - lb * (lx * (double)lox + ly * (double)loy);
+    double Nhi = (double)hib * n2 - lb * (lx * (double)hix + ly * (double)hiy);
     return Nlo * Dhi < Nhi * Dlo;
 }
 
-// Apply the outcome of a 1D LP on line L (row index v) to the state.
-// rows_* point at the LP's first row (global memory) for the rare exact re-check.
-__device__ __forceinline__ void apply_1dlp(LpState& st, int v, const Line& L, const Bounds& B, float cx, float cy,
-                                           const float* rax, const float* ray, const float* rb) {
-    if (B.par_inf) {
-        st.kind = kDead;
-        st.dead_status = kInfeasible;
-        return;
-    }
-    if (B.hi_idx != kNoIdx && B.lo_idx != kNoIdx) {
-        bool inf = B.lo > B.hi;
-        float scale = __builtin_fabsf(B.hi) + __builtin_fabsf(B.lo) + L.pscale;
-        if (__builtin_fabsf(B.hi - B.lo) <= kTieRel * scale) {
-            inf = exact_lo_gt_hi(L, rax[B.lo_idx], ray[B.lo_idx], rb[B.lo_idx], rax[B.hi_idx], ray[B.hi_idx],
-                                 rb[B.hi_idx]);
-        }
-        if (inf) {
-            st.kind = kDead;
-            st.dead_status = kInfeasible;
-            return;
-        }
-    }
-    // direction c prefers along u: first non-zero of (c.u, -u.x, -u.y)
+// Does the 1D LP with bounds (lo, hi) on line L look infeasible, and is the
+// FP32 answer too close to call?
+__device__ __forceinline__ bool near_tie(const Line& L, float hi, float lo) {
+    float scale = __builtin_fabsf(hi) + __builtin_fabsf(lo) + L.pscale;
+    return __builtin_fabsf(hi - lo) <= kTieRel * scale;
+}
+
+// Direction c prefers along u: first non-zero of (c.u, -u.x, -u.y).
+__device__ __forceinline__ bool prefers_up(const Line& L, float cx, float cy) {
     float cu = dot2_exact(cx, cy, L.ux, L.uy);
-    bool up;
-    if (cu != 0.0f) up = cu > 0.0f;
-    else if (L.ly != 0.0f) up = L.ly > 0.0f;
-    else up = L.lx < 0.0f;
-    int pick = up ? B.hi_idx : B.lo_idx;
-    float sig = up ? B.hi : B.lo;
+    if (cu != 0.0f) return cu > 0.0f;
+    if (L.ly != 0.0f) return L.ly > 0.0f;
+    return L.lx < 0.0f;
+}
+
+// New state after a feasible 1D LP on line L (row v) with bounds (lo, hi).
+__device__ __forceinline__ void move_on_line(LpState& st, int v, const Line& L, float hi, float lo, bool up) {
+    float sig = up ? hi : lo;
     st.l = v;
     st.lx = L.lx;
     st.ly = L.ly;
     st.lb = L.lb;
-    if (pick == kNoIdx) {
+    if (__builtin_isinf(sig)) {
         st.kind = kRay;
         st.px = L.p0x;
         st.py = L.p0y;
@@ -232,12 +207,18 @@ __device__ __forceinline__ void apply_1dlp(LpState& st, int v, const Line& L, co
         st.qy = up ? L.uy : -L.uy;
     } else {
         st.kind = kPoint;
-        st.h = pick;
+        st.sig = sig;
+        st.up = up;
         st.px = __builtin_fmaf(sig, L.ux, L.p0x);
         st.py = __builtin_fmaf(sig, L.uy, L.p0y);
         st.qx = 0.0f;
         st.qy = 0.0f;
     }
+}
+
+__device__ __forceinline__ void set_dead(LpState& st, int status) {
+    st.kind = kDead;
+    st.dead_status = status;
 }
 
 __device__ __forceinline__ bool row_less(float ax1, float ay1, float b1, float ax2, float ay2, float b2) {
@@ -246,8 +227,9 @@ __device__ __forceinline__ bool row_less(float ax1, float ay1, float b1, float a
     return b1 < b2;
 }
 
-// Final x*, status for one LP and the output store.
-__device__ __forceinline__ void finish_lp(const Problem& P, int64_t lp, int64_t start, const LpState& st,
+// Final x*, status for one LP and the output store.  For a kPoint state,
+// h is the second row through the vertex.
+__device__ __forceinline__ void finish_lp(const Problem& P, int64_t lp, int64_t start, const LpState& st, int h,
                                           int n1d) {
     float nan = __builtin_nanf("");
     float x = nan, y = nan;
@@ -256,7 +238,7 @@ __device__ __forceinline__ void finish_lp(const Problem& P, int64_t lp, int64_t 
         status = st.dead_status;
     } else if (st.kind == kPoint) {
         float a1x = P.ax[start + st.l], a1y = P.ay[start + st.l], b1 = P.b[start + st.l];
-        float a2x = P.ax[start + st.h], a2y = P.ay[start + st.h], b2 = P.b[start + st.h];
+        float a2x = P.ax[start + h], a2y = P.ay[start + h], b2 = P.b[start + h];
         if (row_less(a2x, a2y, b2, a1x, a1y, b1)) {
             float t;
             t = a1x; a1x = a2x; a2x = t;

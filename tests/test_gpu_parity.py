@@ -18,9 +18,8 @@ from paper_1902_04995_amd import gen
 pytestmark = pytest.mark.gpu
 
 # (variant, lanes_per_lp, slots) combinations exercised; (0, 0) = library default
-SHAPES = [("plain", 0, 0), ("batched", 0, 0), ("batched", 8, 4), ("batched", 8, 9), ("batched", 16, 5),
-          ("batched", 16, 17), ("batched", 32, 9), ("batched", 64, 2), ("batched", 64, 17),
-          ("persistent", 0, 0)]
+SHAPES = [("plain", 0, 0), ("batched", 0, 0), ("batched", 4, 0), ("batched", 8, 0), ("batched", 16, 0),
+          ("batched", 32, 0), ("batched", 64, 0), ("persistent", 0, 0)]
 
 
 def _say(*a):
@@ -91,7 +90,7 @@ def test_parity_tiny_integer_degenerate(rgb, oracle_lib):
     single-point regions); the exact guards must reproduce the exact answer."""
     bt = gen.tiny_integer_batch(4000, m_max=10, K=4, seed=4)
     ref = oracle_lib.solve(bt)
-    for variant, g, s in (("plain", 0, 0), ("batched", 8, 4), ("batched", 64, 2)):
+    for variant, g, s in (("plain", 0, 0), ("batched", 4, 0), ("batched", 64, 0)):
         _say(f"[gpu] case=tiny_int variant={variant} G={g} S={s}")
         _check(bt, ref, _run(rgb, bt, variant, g, s), f"tiny_int/{variant}")
 
@@ -143,12 +142,11 @@ def test_malformed_offsets_are_invalid_not_read(rgb):
 
 
 @pytest.mark.parametrize("m", [1, 63, 64, 65, 300, 1200, 5000])
-def test_overflow_rows_beyond_registers(rgb, oracle_lib, m):
-    """LPs longer than a shape's register capacity take the memory path."""
+def test_sizes_around_group_widths(rgb, oracle_lib, m):
+    """LP sizes around the group widths and well beyond them."""
     bt = gen.uniform_batch(96, m, seed=m)
     ref = oracle_lib.solve(bt)
-    for variant, g, s in (("plain", 0, 0), ("batched", 8, 4), ("batched", 16, 5), ("batched", 64, 2),
-                          ("batched", 64, 17), ("persistent", 0, 0)):
+    for variant, g, s in SHAPES:
         _say(f"[gpu] case=overflow m={m} variant={variant} G={g} S={s}")
         _check(bt, ref, _run(rgb, bt, variant, g, s), f"overflow{m}/{variant}/{g}x{s}")
 

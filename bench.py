@@ -72,11 +72,13 @@ def main():
         ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
         t_start = torch.cuda.Event(enable_timing=True)
         t_end = torch.cuda.Event(enable_timing=True)
+        for a, b in ev:  # create the events so the library can record them
+            a.record(stream)
+            b.record(stream)
+        torch.cuda.synchronize()
         t_start.record(stream)
         for a, b in ev:
-            a.record(stream)
-            dev.solve(variant=variant, out=out, stream=stream, **kw)
-            b.record(stream)
+            dev.solve(variant=variant, out=out, stream=stream, events=(a, b), **kw)
         t_end.record(stream)
         torch.cuda.synchronize()
         total_ms = t_start.elapsed_time(t_end)
@@ -138,7 +140,9 @@ def main():
         "status_counts": status_counts,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "solve", "algorithmic_bytes_per_launch": alg_bytes,
+                     "kernel": "k_persist" if args.variant in ("auto", "persistent") else
+                               ("k_plain" if args.variant == "plain" else "k_group"),
+                     "algorithmic_bytes_per_launch": alg_bytes,
                      "kernel_ms_mean": kern_ms, "kernel_ms_median": kern_med},
         "cpu_baseline": cpu,
     }

@@ -72,13 +72,17 @@ typedef enum {
 /* Kernel families (Sec. 3).  PLAIN is the one-LP-per-lane form the paper
  * calls NaiveRGB; BATCHED gives each LP a group of lanes that scan its rows
  * and split every 1D LP's work units among themselves;
- * PERSISTENT bins LPs by size and runs one persistent launch that takes
- * work from a device queue, largest LPs first.  AUTO = PERSISTENT. */
+ * PERSISTENT bins LPs by size class (lanes per LP chosen per class) and
+ * runs one persistent launch that deals the bulk of the work round-robin and
+ * the tail from a device queue, largest LPs first; BINNED bins the same way
+ * and launches one wave per sub-batch of the queue, leaving the balancing
+ * to the hardware dispatcher.  AUTO = PERSISTENT. */
 typedef enum {
     RGB_VARIANT_AUTO = 0,
     RGB_VARIANT_PLAIN = 1,
     RGB_VARIANT_BATCHED = 2,
-    RGB_VARIANT_PERSISTENT = 3
+    RGB_VARIANT_PERSISTENT = 3,
+    RGB_VARIANT_BINNED = 4
 } rgb_variant_t;
 
 typedef struct rgb_ctx rgb_ctx_t;
@@ -89,10 +93,13 @@ typedef struct {
     int32_t variant;        /* rgb_variant_t */
     int32_t lanes_per_lp;   /* BATCHED: lanes per LP, one of 4, 8, 16, 32, 64 */
     int32_t slots;          /* reserved, must be 0 */
-    int32_t chunk;          /* PERSISTENT: queue entries taken per pop */
+    int32_t chunk;          /* PERSISTENT: sub-batches taken per queue pop */
     int32_t grid;           /* PERSISTENT: workgroups launched */
-    int32_t reserved;
+    int32_t queue_share;    /* PERSISTENT: share of the sub-batches handed out by the device queue,
+                               in 1/1024 (the rest are dealt round-robin); -1 = none */
     int32_t* n_1dlp_out;    /* optional device int32[num_lps]: 1D LPs solved per LP */
+    void* ev_begin;         /* optional hipEvent_t recorded on the stream right before the solve kernel */
+    void* ev_end;           /* optional hipEvent_t recorded right after it (binning kernels excluded) */
 } rgb_solve_opts_t;
 
 /* Version string of the library. */

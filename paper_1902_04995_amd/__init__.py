@@ -18,7 +18,7 @@ import os
 import threading
 
 OPTIMAL, INFEASIBLE, UNBOUNDED, INVALID = 0, 1, 2, 3
-VARIANTS = {"auto": 0, "plain": 1, "batched": 2, "persistent": 3}
+VARIANTS = {"auto": 0, "plain": 1, "batched": 2, "persistent": 3, "binned": 4}
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librgb.so")
@@ -33,8 +33,8 @@ class RgbError(RuntimeError):
 
 class _SolveOpts(ctypes.Structure):
     _fields_ = [("variant", ctypes.c_int32), ("lanes_per_lp", ctypes.c_int32), ("slots", ctypes.c_int32),
-                ("chunk", ctypes.c_int32), ("grid", ctypes.c_int32), ("reserved", ctypes.c_int32),
-                ("n_1dlp_out", ctypes.c_void_p)]
+                ("chunk", ctypes.c_int32), ("grid", ctypes.c_int32), ("queue_share", ctypes.c_int32),
+                ("n_1dlp_out", ctypes.c_void_p), ("ev_begin", ctypes.c_void_p), ("ev_end", ctypes.c_void_p)]
 
 
 def lib():
@@ -115,23 +115,35 @@ def _check_tensor(t, name, dtype, device):
         raise ValueError(f"{name} must be contiguous")
 
 
-def make_opts(variant="auto", lanes_per_lp=0, slots=0, chunk=0, grid=0, n_1dlp=None) -> _SolveOpts:
+def make_opts(variant="auto", lanes_per_lp=0, slots=0, chunk=0, grid=0, n_1dlp=None, events=None,
+              queue_share=0) -> _SolveOpts:
     o = _SolveOpts()
     o.variant = VARIANTS[variant] if isinstance(variant, str) else int(variant)
     o.lanes_per_lp = int(lanes_per_lp)
     o.slots = int(slots)
     o.chunk = int(chunk)
     o.grid = int(grid)
+    o.queue_share = int(queue_share)
     o.n_1dlp_out = n_1dlp.data_ptr() if n_1dlp is not None else None
+    if events is not None:
+        o.ev_begin, o.ev_end = (_event_handle(e) for e in events)
     return o
 
 
+def _event_handle(ev):
+    """Raw hipEvent_t of a torch.cuda.Event (created by recording it once)."""
+    if not ev.cuda_event:
+        ev.record()
+    return ev.cuda_event
+
+
 def solve_batch(offsets, ax, ay, b, cx, cy, *, variant="auto", lanes_per_lp=0, slots=0, chunk=0, grid=0,
-                want_n_1dlp=False, out=None, stream=None, ctx: Context | None = None):
+                queue_share=0, want_n_1dlp=False, out=None, stream=None, ctx: Context | None = None, events=None):
     """Solve a CSR-offset SoA batch held in CUDA tensors (offsets int64[B+1];
     ax, ay, b float32[N]; cx, cy float32[B]).  Enqueues on ``stream`` (default:
     torch's current stream) and returns (x, y, status[, n_1dlp]) tensors that
-    are valid once that stream has run the work."""
+    are valid once that stream has run the work.  ``events`` = (begin, end)
+    torch.cuda.Events recorded around the solve kernel alone."""
     import torch
     dev = offsets.device
     if dev.type != "cuda":
@@ -153,7 +165,7 @@ def solve_batch(offsets, ax, ay, b, cx, cy, *, variant="auto", lanes_per_lp=0, s
     ctx = ctx or context(dev.index or 0)
     if stream is None:
         stream = torch.cuda.current_stream(dev)
-    opts = make_opts(variant, lanes_per_lp, slots, chunk, grid, n1d)
+    opts = make_opts(variant, lanes_per_lp, slots, chunk, grid, n1d, events, queue_share)
     rc = lib().rgb_solve_batch(ctx.handle, B, N, _ptr(offsets), _ptr(ax), _ptr(ay), _ptr(b), _ptr(cx), _ptr(cy),
                                _ptr(x), _ptr(y), _ptr(st), ctypes.byref(opts), ctypes.c_void_p(stream.cuda_stream))
     ctx.check(rc, "rgb_solve_batch")

@@ -114,22 +114,22 @@ __device__ __forceinline__ float dpp_f(float v) {
     return __builtin_bit_cast(float, dpp_i<CTRL>(__builtin_bit_cast(int, v)));
 }
 
-// Butterfly over aligned groups of G lanes: quad_perm xor 1 and xor 2, row
-// half-mirror (8), row mirror (16), swizzle swap 16 (32), then the other half
-// of the wave (64).
-#define RGB_GROUP_REDUCE(NAME, T, OP, DPP)                                         \
-    template <int G>                                                               \
-    __device__ __forceinline__ T NAME(T v) {                                       \
-        if constexpr (G >= 2) v = OP(v, DPP<0xB1>(v));                             \
-        if constexpr (G >= 4) v = OP(v, DPP<0x4E>(v));                             \
-        if constexpr (G >= 8) v = OP(v, DPP<0x141>(v));                            \
-        if constexpr (G >= 16) v = OP(v, DPP<0x140>(v));                           \
-        if constexpr (G >= 32) {                                                   \
+// Butterfly over aligned groups of 2^lg lanes: quad_perm xor 1 and xor 2,
+// row half-mirror (8), row mirror (16), swizzle swap 16 (32), then the other
+// half of the wave (64).  lg is wave-uniform; it is a constant wherever the
+// width is fixed at compile time.
+#define RGB_GROUP_REDUCE(NAME, T, OP, DPP)                                           \
+    __device__ __forceinline__ T NAME(T v, int lg) {                                 \
+        if (lg >= 1) v = OP(v, DPP<0xB1>(v));                                        \
+        if (lg >= 2) v = OP(v, DPP<0x4E>(v));                                        \
+        if (lg >= 3) v = OP(v, DPP<0x141>(v));                                       \
+        if (lg >= 4) v = OP(v, DPP<0x140>(v));                                       \
+        if (lg >= 5) {                                                               \
             int s = __builtin_amdgcn_ds_swizzle(__builtin_bit_cast(int, v), 0x401F); \
-            v = OP(v, __builtin_bit_cast(T, s));                                   \
-        }                                                                          \
-        if constexpr (G >= 64) v = OP(v, __shfl_xor(v, 32));                       \
-        return v;                                                                  \
+            v = OP(v, __builtin_bit_cast(T, s));                                     \
+        }                                                                            \
+        if (lg >= 6) v = OP(v, __shfl_xor(v, 32));                                   \
+        return v;                                                                    \
     }
 
 __device__ __forceinline__ float fmin_(float a, float b) { return __builtin_fminf(a, b); }
@@ -140,33 +140,36 @@ RGB_GROUP_REDUCE(group_max, float, fmax_, dpp_f)
 RGB_GROUP_REDUCE(group_min_i, int, imin_, dpp_i)
 #undef RGB_GROUP_REDUCE
 
-template <int G>
-__device__ __forceinline__ uint64_t group_mask(int gbase) {
-    if constexpr (G == 64) return ~0ull;
-    else return ((1ull << G) - 1ull) << gbase;
+__device__ __forceinline__ uint64_t group_mask(int lg, int gbase) {
+    return lg >= 6 ? ~0ull : (((1ull << (1 << lg)) - 1ull) << gbase);
 }
 
 // Smallest row h < v of the LP whose bound on line L equals `target` on the
-// given side; all G lanes of the group must be active.
-template <int G>
+// given side; all lanes of the group must be active.
 __device__ __forceinline__ int group_find(const float* rax, const float* ray, const float* rb, int v, const Line& L,
-                                          float target, bool up, int gl) {
+                                          float target, bool up, int gl, int lg) {
     int best = kNoIdx;
-    for (int h = gl; h < v; h += G) {
+    for (int h = gl; h < v; h += (1 << lg)) {
         float D;
         float s = wu_sigma(rax[h], ray[h], rb[h], L, D);
         bool hit = (up ? D > 0.0f : D < 0.0f) && s == target;
         best = (hit && h < best) ? h : best;
     }
-    return group_min_i<G>(best);
+    return group_min_i(best, lg);
 }
 
-template <int G>
-__device__ __forceinline__ void solve_group(const Problem& P, int64_t lp) {
+// Solve the LP `lp` (-1: none) with a group of G = 2^lg lanes; every lane of
+// the wave calls this together, each group with its own LP.  LGC >= 0 fixes
+// lg at compile time; LGC = -1 takes it from lg_rt (one body for any width,
+// which keeps the persistent kernel's register count at one width's).
+template <int LGC>
+__device__ __forceinline__ void solve_group(const Problem& P, int64_t lp, int lg_rt = 0) {
+    const int lg = LGC >= 0 ? LGC : lg_rt;
+    const int G = 1 << lg;
     const int lane = __lane_id();
     const int gl = lane & (G - 1);
     const int gbase = lane & ~(G - 1);
-    const uint64_t gmask = group_mask<G>(gbase);
+    const uint64_t gmask = group_mask(lg, gbase);
 
     int64_t start = 0;
     int m = 0;
@@ -226,8 +229,8 @@ __device__ __forceinline__ void solve_group(const Problem& P, int64_t lp) {
                 float hi = __builtin_huge_valf(), lo = -__builtin_huge_valf();
                 bool par = false;
                 for (int h = gl; h < v; h += G) work_unit(rax[h], ray[h], rb[h], L, hi, lo, par);
-                hi = group_min<G>(hi);
-                lo = group_max<G>(lo);
+                hi = group_min(hi, lg);
+                lo = group_max(lo, lg);
                 par = (__ballot(par) & gmask) != 0;
                 if (par) {
                     set_dead(st, kInfeasible);
@@ -236,8 +239,8 @@ __device__ __forceinline__ void solve_group(const Problem& P, int64_t lp) {
                     if (!__builtin_isinf(hi) && !__builtin_isinf(lo)) {
                         inf = lo > hi;
                         if (near_tie(L, hi, lo)) {
-                            int il = group_find<G>(rax, ray, rb, v, L, lo, false, gl);
-                            int ih = group_find<G>(rax, ray, rb, v, L, hi, true, gl);
+                            int il = group_find(rax, ray, rb, v, L, lo, false, gl, lg);
+                            int ih = group_find(rax, ray, rb, v, L, hi, true, gl, lg);
                             if (il != kNoIdx && ih != kNoIdx)
                                 inf = exact_lo_gt_hi(L, rax[il], ray[il], rb[il], rax[ih], ray[ih], rb[ih]);
                         }
@@ -260,7 +263,7 @@ __device__ __forceinline__ void solve_group(const Problem& P, int64_t lp) {
         if (st.kind == kPoint) {
             Line L;
             make_line(L, rax[st.l], ray[st.l], rb[st.l]);
-            h = group_find<G>(rax, ray, rb, st.l, L, st.sig, st.up, gl);
+            h = group_find(rax, ray, rb, st.l, L, st.sig, st.up, gl, lg);
             if (h == kNoIdx) h = st.l;  // cannot happen (the bound came from these bits); x is NaN then
         }
     }
@@ -273,7 +276,185 @@ __global__ __launch_bounds__(256) void k_group(Problem P) {
     int64_t q = (int64_t)blockIdx.x * LPS_PER_BLOCK + threadIdx.x / G;
     int64_t lp = -1;
     if (q < P.num_lps) lp = P.order ? (int64_t)P.order[q] : q;
-    solve_group<G>(P, lp);
+    constexpr int LG = G == 4 ? 2 : G == 8 ? 3 : G == 16 ? 4 : G == 32 ? 5 : 6;
+    solve_group<LG>(P, lp);
+}
+
+// ---------------------------------------------------------------------------
+// persistent: size bins + device work queue
+// ---------------------------------------------------------------------------
+// Size class of an LP with m rows: ceil(log2 m), 0 for m <= 1, capped.
+__device__ __forceinline__ int size_class(int m) {
+    if (m <= 1) return 0;
+    int c = 32 - __builtin_clz((unsigned)(m - 1));
+    return c < kClasses ? c : kClasses - 1;
+}
+
+// Binning: LPs are split into kBinBlocks contiguous ranges; each block counts
+// its LPs per class in LDS, one block turns the counts into queue offsets
+// (classes largest first, then block order), and the scatter pass writes the
+// queue.  No global atomics, so no contention however skewed the sizes.
+__device__ __forceinline__ void bin_range(int64_t n, int64_t& lo, int64_t& hi) {
+    int64_t per = (n + gridDim.x - 1) / gridDim.x;
+    lo = (int64_t)blockIdx.x * per;
+    hi = lo + per < n ? lo + per : n;
+}
+
+__global__ __launch_bounds__(256) void k_bin(Problem P, Workspace W) {
+    __shared__ int hist[kClasses];
+    if (threadIdx.x < kClasses) hist[threadIdx.x] = 0;
+    __syncthreads();
+    int64_t lo, hi;
+    bin_range(P.num_lps, lo, hi);
+    for (int64_t lp = lo + threadIdx.x; lp < hi; lp += blockDim.x) {
+        int64_t start;
+        int m;
+        lp_range(P, lp, start, m);
+        int c = size_class(m);
+        W.cls[lp] = (uint8_t)c;
+        atomicAdd(&hist[c], 1);
+    }
+    __syncthreads();
+    if (threadIdx.x < kClasses) W.blocks[blockIdx.x * kClasses + threadIdx.x] = hist[threadIdx.x];
+}
+
+// One block of kBinBlocks threads: thread t owns bin block t.  Inclusive
+// Hillis-Steele scan over t for all classes at once, then class bases, then
+// the sub-batch table of the queue (a sub-batch is 64/G LPs of one class).
+__global__ __launch_bounds__(kBinBlocks) void k_scan(Workspace W, PersistPlan plan) {
+    __shared__ int s[2][kClasses][kBinBlocks];
+    const int t = threadIdx.x;
+    int own[kClasses];
+#pragma unroll
+    for (int c = 0; c < kClasses; ++c) {
+        own[c] = W.blocks[t * kClasses + c];
+        s[0][c][t] = own[c];
+    }
+    __syncthreads();
+    int src = 0;
+    for (int d = 1; d < kBinBlocks; d <<= 1) {
+#pragma unroll
+        for (int c = 0; c < kClasses; ++c) s[src ^ 1][c][t] = s[src][c][t] + (t >= d ? s[src][c][t - d] : 0);
+        src ^= 1;
+        __syncthreads();
+    }
+    int base = 0;
+    for (int c = kClasses - 1; c >= 0; --c) {
+        int incl = s[src][c][t];
+        W.blocks[t * kClasses + c] = base + incl - own[c];
+        base += s[src][c][kBinBlocks - 1];
+    }
+    if (t == 0) {
+        QueueHeader* Q = W.q;
+        int e = 0, sb = 0;
+        for (int j = 0; j < kClasses; ++j) {  // queue order: largest class first
+            int c = kClasses - 1 - j;
+            int n = s[src][c][kBinBlocks - 1];
+            int lg = plan.log2_lanes[c];
+            Q->e_start[j] = e;
+            Q->e_end[j] = e + n;
+            Q->lg[j] = lg;
+            sb += (n + (64 >> lg) - 1) >> (6 - lg);
+            Q->sb_end[j] = sb;
+            e += n;
+        }
+        Q->num_sb = sb;
+        int dyn = (int)(((int64_t)sb * plan.dyn_frac_1024) >> 10);
+        Q->dyn_begin = sb - dyn;
+        for (int x = 0; x < kQueues; ++x) W.heads[x * kHeadStride] = 0;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_scatter(Problem P, Workspace W) {
+    __shared__ int cur[kClasses];
+    if (threadIdx.x < kClasses) cur[threadIdx.x] = W.blocks[blockIdx.x * kClasses + threadIdx.x];
+    __syncthreads();
+    int64_t lo, hi;
+    bin_range(P.num_lps, lo, hi);
+    for (int64_t lp = lo + threadIdx.x; lp < hi; lp += blockDim.x) {
+        int c = W.cls[lp] & (kClasses - 1);
+        int pos = atomicAdd(&cur[c], 1);
+        if (pos >= 0 && pos < P.num_lps) W.order[pos] = (int32_t)lp;
+    }
+}
+
+// Queue position of sub-batch k: its class slot j (queue order).
+__device__ __forceinline__ int sub_batch_slot(const QueueHeader& Q, int k) {
+    int j = 0;
+    while (j < kClasses - 1 && k >= Q.sb_end[j]) ++j;
+    return j;
+}
+
+// Solve sub-batch k (class slot j) of the queue: 64/G LPs of one class,
+// G = 2^lg with lg = Q.lg[j] (fixed at compile time when LGC >= 0).
+template <int LGC>
+__device__ __forceinline__ void run_sub_batch(const Problem& P, const Workspace& W, const QueueHeader& Q, int k,
+                                              int j) {
+    const int lg = LGC >= 0 ? LGC : Q.lg[j];
+    int sb0 = j ? Q.sb_end[j - 1] : 0;
+    int first = Q.e_start[j] + ((k - sb0) << (6 - lg));
+    int q = first + (__lane_id() >> lg);
+    int64_t lp = q < Q.e_end[j] ? (int64_t)W.order[q] : -1;
+    if (lp >= P.num_lps) lp = -1;  // never read outside the batch, whatever the queue holds
+    solve_group<LGC>(P, lp, lg);
+}
+
+__device__ __forceinline__ void load_header(QueueHeader& Qs, const Workspace& W) {
+    if (threadIdx.x < sizeof(QueueHeader) / 4)
+        reinterpret_cast<int*>(&Qs)[threadIdx.x] = reinterpret_cast<const int*>(W.q)[threadIdx.x];
+    __syncthreads();
+}
+
+// Persistent solve.  Sub-batches [0, dyn_begin) are dealt round-robin to the
+// waves of the grid (the queue is sorted largest class first, so every wave
+// gets a similar mix); the rest go through the device queue, split into
+// kQueues interleaved parts with one head each, so that the pops of one
+// XCD's waves (workgroups are spread over the XCDs round-robin) mostly hit
+// their own counter.  A wave whose part is drained takes from the others,
+// `chunk` sub-batches per pop.  Every wave exits once all parts are drained.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_persist(Problem P, Workspace W,
+                                                                                         PersistPlan plan) {
+    __shared__ QueueHeader Qs;
+    load_header(Qs, W);
+    const QueueHeader& Q = Qs;
+    const int waves = (int)(gridDim.x * (blockDim.x >> 6));
+    const int wid = (int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
+    for (int k = wid; k < Q.dyn_begin; k += waves) run_sub_batch<-1>(P, W, Q, k, sub_batch_slot(Q, k));
+    const int chunk = plan.chunk > 0 ? plan.chunk : 1;
+    const int ndyn = Q.num_sb - Q.dyn_begin;
+    for (int t = 0; t < kQueues; ++t) {
+        const int x = (int)((blockIdx.x + t) % kQueues);
+        const int len = ndyn > x ? (ndyn - x + kQueues - 1) / kQueues : 0;  // entries of part x
+        while (true) {
+            int i0 = 0;
+            if (__lane_id() == 0) i0 = atomicAdd(&W.heads[x * kHeadStride], chunk);
+            i0 = __builtin_amdgcn_readfirstlane(i0);
+            if (i0 >= len) break;
+            int i1 = min(i0 + chunk, len);
+            for (int i = i0; i < i1; ++i) {
+                int k = Q.dyn_begin + x + i * kQueues;
+                run_sub_batch<-1>(P, W, Q, k, sub_batch_slot(Q, k));
+            }
+        }
+    }
+}
+
+// Binned, non-persistent: one wave per sub-batch in queue order (largest LPs
+// first); the grid is an upper bound and surplus waves exit at once.  The
+// hardware dispatcher starts a new wave wherever one finishes.
+__global__ __launch_bounds__(256) void k_binned(Problem P, Workspace W) {
+    __shared__ QueueHeader Qs;
+    load_header(Qs, W);
+    const int k = (int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
+    if (k >= Qs.num_sb) return;
+    int j = sub_batch_slot(Qs, k);
+    switch (Qs.lg[j]) {
+        case 2: run_sub_batch<2>(P, W, Qs, k, j); break;
+        case 3: run_sub_batch<3>(P, W, Qs, k, j); break;
+        case 4: run_sub_batch<4>(P, W, Qs, k, j); break;
+        case 5: run_sub_batch<5>(P, W, Qs, k, j); break;
+        default: run_sub_batch<6>(P, W, Qs, k, j); break;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -296,6 +477,31 @@ static hipError_t launch_group_t(const Problem& P, hipStream_t stream) {
 
 bool group_supported(int g) {
     return g == 4 || g == 8 || g == 16 || g == 32 || g == 64;
+}
+
+hipError_t launch_persistent(const Problem& P, const Workspace& W, const PersistPlan& plan, int grid, bool binned,
+                             hipStream_t stream, hipEvent_t ev_begin, hipEvent_t ev_end) {
+    if (P.num_lps == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_bin, dim3(kBinBlocks), dim3(256), 0, stream, P, W);
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(kBinBlocks), 0, stream, W, plan);
+    hipLaunchKernelGGL(k_scatter, dim3(kBinBlocks), dim3(256), 0, stream, P, W);
+    if (ev_begin) (void)hipEventRecord(ev_begin, stream);
+    if (binned) {
+        // at most one sub-batch per LP plus one partial sub-batch per class
+        int64_t max_sb = P.num_lps + kClasses;
+        int64_t blocks = (max_sb + 3) / 4;
+        hipLaunchKernelGGL(k_binned, dim3((unsigned)blocks), dim3(256), 0, stream, P, W);
+    } else {
+        hipLaunchKernelGGL(k_persist, dim3(grid), dim3(256), 0, stream, P, W, plan);
+    }
+    if (ev_end) (void)hipEventRecord(ev_end, stream);
+    return hipGetLastError();
+}
+
+int persist_blocks_per_cu() {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_persist, 256, 0) != hipSuccess) return 1;
+    return n > 0 ? n : 1;
 }
 
 hipError_t launch_group(const Problem& P, int g, hipStream_t stream) {

@@ -28,6 +28,12 @@ WORKLOADS = {
 }
 
 
+def kernel_name(variant, tuning):
+    v = tuning["variant"] if (variant == "auto" and tuning) else variant
+    v = "persistent" if v == "auto" else v
+    return {"persistent": "k_persist", "binned": "k_binned", "batched": "k_group", "plain": "k_plain"}[v]
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -36,9 +42,10 @@ def main():
     ap.add_argument("--workload", default="uniform", choices=sorted(WORKLOADS))
     ap.add_argument("--variant", default="auto")
     ap.add_argument("--lanes", type=int, default=0)
-    ap.add_argument("--slots", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-kernel comparison")
+    ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (AUTO uses the default plan)")
+    ap.add_argument("--tune-budget-ms", type=float, default=3000.0)
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -64,6 +71,12 @@ def main():
            torch.empty(bt.num_lps, dtype=torch.float32, device="cuda"),
            torch.empty(bt.num_lps, dtype=torch.int32, device="cuda"))
     alg_bytes = bt.algorithmic_bytes()
+    tuning = None
+    if args.variant == "auto" and not args.no_tune:
+        t0 = time.time()
+        best = dev.autotune(reps=3, budget_ms=args.tune_budget_ms, out=out, stream=stream)
+        tuning = best.to_dict()
+        print(f"[bench] autotune {time.time() - t0:.1f}s -> {tuning}", file=sys.stderr, flush=True)
 
     def run(variant, steps, warmup, **kw):
         for _ in range(warmup):
@@ -85,7 +98,7 @@ def main():
         per = [a.elapsed_time(b) for a, b in ev]
         return total_ms / steps, float(np.mean(per)), float(np.median(per)), per
 
-    kw = dict(lanes_per_lp=args.lanes, slots=args.slots)
+    kw = dict(lanes_per_lp=args.lanes)
     ms_step, kern_ms, kern_med, per = run(args.variant, args.steps, args.warmup, **kw)
     print(f"[bench] {args.variant}: {ms_step:.3f} ms/step, kernel mean {kern_ms:.3f} ms median {kern_med:.3f} ms",
           file=sys.stderr, flush=True)
@@ -132,7 +145,7 @@ def main():
         "data": "synthetic (seeded generator, inputs resident in HBM)",
         "config": {"workload": f"{args.workload}: {WORKLOADS[args.workload]}", "num_lps": bt.num_lps,
                    "half_planes": bt.num_constraints, "variant": args.variant,
-                   "lanes_per_lp": args.lanes, "slots": args.slots},
+                   "lanes_per_lp": args.lanes, "tuning": tuning},
         "constraints_per_s": bt.num_constraints / (ms_step / 1e3),
         "hbm_gbs": achieved,
         "plain": plain,
@@ -140,8 +153,7 @@ def main():
         "status_counts": status_counts,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_persist" if args.variant in ("auto", "persistent") else
-                               ("k_plain" if args.variant == "plain" else "k_group"),
+                     "kernel": kernel_name(args.variant, tuning),
                      "algorithmic_bytes_per_launch": alg_bytes,
                      "kernel_ms_mean": kern_ms, "kernel_ms_median": kern_med},
         "cpu_baseline": cpu,

@@ -102,6 +102,20 @@ typedef struct {
     void* ev_end;           /* optional hipEvent_t recorded right after it (binning kernels excluded) */
 } rgb_solve_opts_t;
 
+/* A launch configuration: kernel family and shape.  rgb_autotune() fills one
+ * by measurement; AUTO solves use the context's current one. */
+typedef struct {
+    int32_t variant;        /* RGB_VARIANT_PERSISTENT, RGB_VARIANT_BINNED or RGB_VARIANT_BATCHED */
+    int32_t log2_lanes[16]; /* PERSISTENT/BINNED: lanes per LP = 2^v (v in 2..6) for size class c,
+                               which holds LPs with 2^(c-1) < m <= 2^c rows (class 0: m <= 1,
+                               class 15: m > 2^14) */
+    int32_t batched_lanes;  /* BATCHED: lanes per LP (4, 8, 16, 32 or 64) */
+    int32_t queue_share;    /* PERSISTENT: sub-batches handed out by the device queue, in 1/1024 */
+    int32_t chunk;          /* PERSISTENT: sub-batches per queue pop (>= 1) */
+    int32_t grid;           /* PERSISTENT: workgroups, 0 = all that fit on the device at once */
+    float ms;               /* rgb_autotune: measured time of one solve with this configuration */
+} rgb_tuning_t;
+
 /* Version string of the library. */
 const char* rgb_version(void);
 
@@ -128,6 +142,39 @@ rgb_err_t rgb_solve_batch(rgb_ctx_t* ctx, int64_t num_lps, int64_t num_constrain
                           const int64_t* offsets, const float* ax, const float* ay, const float* b,
                           const float* cx, const float* cy, float* x_out, float* y_out,
                           int32_t* status_out, const rgb_solve_opts_t* opts, void* stream);
+
+/* Read or replace the configuration AUTO solves on ctx use.  set validates
+ * every field (INVALID_ARG otherwise). */
+rgb_err_t rgb_ctx_get_tuning(const rgb_ctx_t* ctx, rgb_tuning_t* out);
+rgb_err_t rgb_ctx_set_tuning(rgb_ctx_t* ctx, const rgb_tuning_t* tuning);
+
+/* Choose the fastest configuration for this batch by measurement and make
+ * it ctx's AUTO configuration.  Arguments as rgb_solve_batch (the outputs
+ * are overwritten by the trial solves); the kernel families are compared
+ * first, then lanes per LP class by class (classes holding >= 4% of the rows,
+ * largest first), then the queue share and chunk of the persistent kernel.
+ * Each candidate is timed `reps` times with HIP events on `stream` (the
+ * median counts) until `budget_ms` of wall time is spent.  Blocks until done.
+ * *best (may be NULL) receives the winner.  Errors as rgb_solve_batch. */
+rgb_err_t rgb_autotune(rgb_ctx_t* ctx, int64_t num_lps, int64_t num_constraints, const int64_t* offsets,
+                       const float* ax, const float* ay, const float* b, const float* cx, const float* cy,
+                       float* x_out, float* y_out, int32_t* status_out, int32_t reps, double budget_ms,
+                       void* stream, rgb_tuning_t* best);
+
+/* A solve captured once as a HIP graph (binning, queue set-up and the solve
+ * kernel) and replayed with rgb_plan_launch: same buffers, same launch
+ * configuration, no host-side argument work.  The plan owns its workspace,
+ * so launches of different plans may overlap; launches of one plan must not
+ * (issue them on one stream).  Buffers must stay valid while the plan
+ * exists.  The configuration is ctx's at creation time unless opts selects
+ * one.  opts->n_1dlp_out and the events are captured too. */
+typedef struct rgb_plan rgb_plan_t;
+rgb_err_t rgb_plan_create(rgb_ctx_t* ctx, int64_t num_lps, int64_t num_constraints, const int64_t* offsets,
+                          const float* ax, const float* ay, const float* b, const float* cx, const float* cy,
+                          float* x_out, float* y_out, int32_t* status_out, const rgb_solve_opts_t* opts,
+                          rgb_plan_t** out);
+rgb_err_t rgb_plan_launch(rgb_plan_t* plan, void* stream);
+rgb_err_t rgb_plan_destroy(rgb_plan_t* plan);
 
 #ifdef __cplusplus
 }

@@ -37,6 +37,32 @@ class _SolveOpts(ctypes.Structure):
                 ("n_1dlp_out", ctypes.c_void_p), ("ev_begin", ctypes.c_void_p), ("ev_end", ctypes.c_void_p)]
 
 
+class Tuning(ctypes.Structure):
+    """rgb_tuning_t: a launch configuration (see include/rgb.h)."""
+    _fields_ = [("variant", ctypes.c_int32), ("log2_lanes", ctypes.c_int32 * 16), ("batched_lanes", ctypes.c_int32),
+                ("queue_share", ctypes.c_int32), ("chunk", ctypes.c_int32), ("grid", ctypes.c_int32),
+                ("ms", ctypes.c_float)]
+
+    def to_dict(self):
+        return {"variant": {v: k for k, v in VARIANTS.items()}.get(self.variant, self.variant),
+                "log2_lanes": list(self.log2_lanes), "batched_lanes": self.batched_lanes,
+                "queue_share": self.queue_share, "chunk": self.chunk, "grid": self.grid, "ms": self.ms}
+
+    @classmethod
+    def from_dict(cls, d):
+        t = cls()
+        v = d["variant"]
+        t.variant = VARIANTS[v] if isinstance(v, str) else int(v)
+        for i, x in enumerate(d["log2_lanes"]):
+            t.log2_lanes[i] = int(x)
+        t.batched_lanes = int(d["batched_lanes"])
+        t.queue_share = int(d["queue_share"])
+        t.chunk = int(d["chunk"])
+        t.grid = int(d.get("grid", 0))
+        t.ms = float(d.get("ms", 0.0))
+        return t
+
+
 def lib():
     """Load librgb.so (after torch, so both use one HIP runtime)."""
     global _lib
@@ -59,6 +85,18 @@ def lib():
         L.rgb_ctx_last_error.restype = ctypes.c_char_p
         L.rgb_solve_batch.argtypes = [P, I64, I64] + [P] * 9 + [ctypes.POINTER(_SolveOpts), P]
         L.rgb_solve_batch.restype = I32
+        L.rgb_ctx_get_tuning.argtypes = [P, ctypes.POINTER(Tuning)]
+        L.rgb_ctx_get_tuning.restype = I32
+        L.rgb_ctx_set_tuning.argtypes = [P, ctypes.POINTER(Tuning)]
+        L.rgb_ctx_set_tuning.restype = I32
+        L.rgb_autotune.argtypes = [P, I64, I64] + [P] * 9 + [I32, ctypes.c_double, P, ctypes.POINTER(Tuning)]
+        L.rgb_autotune.restype = I32
+        L.rgb_plan_create.argtypes = [P, I64, I64] + [P] * 9 + [ctypes.POINTER(_SolveOpts), ctypes.POINTER(P)]
+        L.rgb_plan_create.restype = I32
+        L.rgb_plan_launch.argtypes = [P, P]
+        L.rgb_plan_launch.restype = I32
+        L.rgb_plan_destroy.argtypes = [P]
+        L.rgb_plan_destroy.restype = I32
         _lib = L
     return _lib
 
@@ -79,6 +117,18 @@ class Context:
         if rc != 0:
             msg = lib().rgb_ctx_last_error(self.handle).decode()
             raise RgbError(f"{what} failed ({rc}): {msg}")
+
+    @property
+    def tuning(self) -> "Tuning":
+        t = Tuning()
+        self.check(lib().rgb_ctx_get_tuning(self.handle, ctypes.byref(t)), "rgb_ctx_get_tuning")
+        return t
+
+    @tuning.setter
+    def tuning(self, t):
+        if isinstance(t, dict):
+            t = Tuning.from_dict(t)
+        self.check(lib().rgb_ctx_set_tuning(self.handle, ctypes.byref(t)), "rgb_ctx_set_tuning")
 
     def close(self):
         if self.handle:
@@ -174,6 +224,77 @@ def solve_batch(offsets, ax, ay, b, cx, cy, *, variant="auto", lanes_per_lp=0, s
     return x, y, st
 
 
+def _batch_args(offsets, ax, ay, b, cx, cy, out):
+    import torch
+    dev = offsets.device
+    if dev.type != "cuda":
+        raise ValueError("needs CUDA tensors")
+    _check_tensor(offsets, "offsets", torch.int64, dev)
+    for name, t in (("ax", ax), ("ay", ay), ("b", b), ("cx", cx), ("cy", cy)):
+        _check_tensor(t, name, torch.float32, dev)
+    B = offsets.numel() - 1
+    N = ax.numel()
+    if B < 0 or ay.numel() != N or b.numel() != N or cx.numel() != B or cy.numel() != B:
+        raise ValueError("inconsistent batch shapes")
+    if out is None:
+        out = (torch.empty(B, dtype=torch.float32, device=dev), torch.empty(B, dtype=torch.float32, device=dev),
+               torch.empty(B, dtype=torch.int32, device=dev))
+    x, y, st = out
+    return dev, B, N, [_ptr(offsets), _ptr(ax), _ptr(ay), _ptr(b), _ptr(cx), _ptr(cy), _ptr(x), _ptr(y), _ptr(st)], out
+
+
+def autotune(offsets, ax, ay, b, cx, cy, *, reps=3, budget_ms=2000.0, out=None, stream=None,
+             ctx: Context | None = None) -> Tuning:
+    """Measure the kernel families and launch shapes on this batch and make the
+    fastest one the context's AUTO configuration (rgb_autotune)."""
+    import torch
+    dev, B, N, args, out = _batch_args(offsets, ax, ay, b, cx, cy, out)
+    ctx = ctx or context(dev.index or 0)
+    if stream is None:
+        stream = torch.cuda.current_stream(dev)
+    best = Tuning()
+    rc = lib().rgb_autotune(ctx.handle, B, N, *args, int(reps), float(budget_ms), ctypes.c_void_p(stream.cuda_stream),
+                            ctypes.byref(best))
+    ctx.check(rc, "rgb_autotune")
+    return best
+
+
+class Plan:
+    """A solve captured as a HIP graph (rgb_plan_create) over fixed buffers."""
+
+    def __init__(self, offsets, ax, ay, b, cx, cy, *, variant="auto", lanes_per_lp=0, chunk=0, grid=0,
+                 queue_share=0, out=None, want_n_1dlp=False, ctx: Context | None = None):
+        import torch
+        dev, B, N, args, out = _batch_args(offsets, ax, ay, b, cx, cy, out)
+        self.ctx = ctx or context(dev.index or 0)
+        self.out = out
+        self.n_1dlp = torch.empty(B, dtype=torch.int32, device=dev) if want_n_1dlp else None
+        self._keep = (offsets, ax, ay, b, cx, cy)
+        opts = make_opts(variant, lanes_per_lp, 0, chunk, grid, self.n_1dlp, None, queue_share)
+        h = ctypes.c_void_p()
+        rc = lib().rgb_plan_create(self.ctx.handle, B, N, *args, ctypes.byref(opts), ctypes.byref(h))
+        self.ctx.check(rc, "rgb_plan_create")
+        self.handle = h
+
+    def launch(self, stream=None):
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream(self.out[0].device)
+        self.ctx.check(lib().rgb_plan_launch(self.handle, ctypes.c_void_p(stream.cuda_stream)), "rgb_plan_launch")
+        return self.out
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().rgb_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class DeviceBatch:
     """A gen.Batch copied to device memory."""
 
@@ -188,3 +309,9 @@ class DeviceBatch:
 
     def solve(self, **kw):
         return solve_batch(self.offsets, self.ax, self.ay, self.b, self.cx, self.cy, **kw)
+
+    def autotune(self, **kw):
+        return autotune(self.offsets, self.ax, self.ay, self.b, self.cx, self.cy, **kw)
+
+    def plan(self, **kw):
+        return Plan(self.offsets, self.ax, self.ay, self.b, self.cx, self.cy, **kw)

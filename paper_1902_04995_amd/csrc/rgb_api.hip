@@ -1,9 +1,13 @@
-// C ABI of the batched 2D LP solver: argument checks, context, dispatch.
+// C ABI of the batched 2D LP solver: argument checks, contexts, dispatch,
+// autotuning and captured plans.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <chrono>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <new>
 #include <string>
 #include <vector>
 
@@ -12,8 +16,8 @@
 
 namespace {
 
-// Workspace of the solves issued on one stream (solves on one stream run in
-// order, so they can share it).
+// Device workspace of the solves issued on one stream (solves on one stream
+// run in order, so they can share it), or of one plan.
 struct WsSlot {
     void* stream = nullptr;
     void* mem = nullptr;
@@ -29,9 +33,16 @@ struct rgb_ctx {
     int device = 0;
     int num_cus = 0;
     int persist_blocks_per_cu = 1;
-    rgb::PersistPlan plan{};
+    rgb_tuning_t tuning{};
     std::vector<WsSlot> slots;
     std::string last_error;
+};
+
+struct rgb_plan {
+    rgb_ctx_t* ctx = nullptr;
+    WsSlot ws;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
 };
 
 namespace {
@@ -48,7 +59,7 @@ rgb_err_t fail(rgb_ctx_t* ctx, rgb_err_t code, const char* fmt, ...) {
     return code;
 }
 
-// Makes ctx->device current for the lifetime of the guard.
+// Makes a device current for the lifetime of the guard.
 struct DeviceGuard {
     int prev = -1;
     bool ok = false;
@@ -61,29 +72,78 @@ struct DeviceGuard {
     }
 };
 
-constexpr int kDefaultLanes = 16;
-constexpr int kDefaultChunk = 1;
-constexpr int kDefaultDynFrac = 128;  // last 1/8 of the sub-batches go through the queue
+bool lanes_ok(int g) { return g == 4 || g == 8 || g == 16 || g == 32 || g == 64; }
 
-// Lanes per LP by size class (class c holds 2^(c-1) < m <= 2^c).
-void default_plan(rgb::PersistPlan& p) {
+// Lanes per LP by size class before any tuning.
+void default_tuning(rgb_tuning_t& t) {
+    std::memset(&t, 0, sizeof(t));
+    t.variant = RGB_VARIANT_PERSISTENT;
     for (int c = 0; c < rgb::kClasses; ++c) {
-        int g = 64;
-        if (c <= 4) g = 4;
-        else if (c <= 6) g = 8;
-        else if (c <= 8) g = 16;
-        else if (c <= 9) g = 32;
-        p.log2_lanes[c] = __builtin_ctz(g);
+        int lg = 6;
+        if (c <= 4) lg = 2;
+        else if (c <= 6) lg = 3;
+        else if (c <= 8) lg = 4;
+        else if (c <= 9) lg = 5;
+        t.log2_lanes[c] = lg;
     }
-    p.chunk = kDefaultChunk;
-    p.dyn_frac_1024 = kDefaultDynFrac;
+    t.batched_lanes = 16;
+    t.queue_share = 128;
+    t.chunk = 1;
+    t.grid = 0;
+}
+
+bool tuning_valid(const rgb_tuning_t& t) {
+    if (t.variant != RGB_VARIANT_PERSISTENT && t.variant != RGB_VARIANT_BINNED && t.variant != RGB_VARIANT_BATCHED)
+        return false;
+    for (int c = 0; c < rgb::kClasses; ++c)
+        if (t.log2_lanes[c] < 2 || t.log2_lanes[c] > 6) return false;
+    return lanes_ok(t.batched_lanes) && t.queue_share >= 0 && t.queue_share <= 1024 && t.chunk >= 1 &&
+           t.grid >= 0;
 }
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
-// Workspace for a solve of num_lps LPs on `stream`; grows with hipMalloc
-// (never while the stream is being captured).
-rgb_err_t get_workspace(rgb_ctx_t* ctx, void* stream, int64_t num_lps, rgb::Workspace& out) {
+// (Re)allocate a workspace for num_lps LPs.  Never during capture.
+rgb_err_t grow_workspace(rgb_ctx_t* ctx, WsSlot& slot, int64_t num_lps) {
+    if (slot.mem && slot.cap >= num_lps) return RGB_OK;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (slot.stream && hipStreamIsCapturing(reinterpret_cast<hipStream_t>(slot.stream), &cs) == hipSuccess &&
+        cs != hipStreamCaptureStatusNone)
+        return fail(ctx, RGB_ERR_INVALID_ARG, "workspace must grow but the stream is being captured");
+    static_assert(sizeof(rgb::QueueHeader) <= 1024, "queue header");
+    static_assert(rgb::kQueues * rgb::kHeadStride * 4 <= 1024, "queue heads");
+    int64_t cap = num_lps < 1024 ? 1024 : num_lps + num_lps / 4;
+    size_t head_bytes = 2048;
+    size_t blocks_off = head_bytes;
+    size_t order_off = blocks_off + (size_t)rgb::kBinBlocks * rgb::kClasses * 4;
+    size_t cls_off = align_up(order_off + (size_t)cap * 4, 256);
+    size_t total = cls_off + align_up((size_t)cap, 256);
+    if (slot.mem) {
+        if (slot.stream) (void)hipStreamSynchronize(reinterpret_cast<hipStream_t>(slot.stream));
+        else (void)hipDeviceSynchronize();
+        (void)hipFree(slot.mem);
+        slot.mem = nullptr;
+        slot.cap = 0;
+    }
+    void* mem = nullptr;
+    if (hipMalloc(&mem, total) != hipSuccess) return fail(ctx, RGB_ERR_OOM, "workspace of %zu bytes", total);
+    if (hipMemset(mem, 0, head_bytes) != hipSuccess) {
+        (void)hipFree(mem);
+        return fail(ctx, RGB_ERR_DEVICE, "workspace init failed");
+    }
+    char* base = static_cast<char*>(mem);
+    slot.mem = mem;
+    slot.cap = cap;
+    slot.ws.q = reinterpret_cast<rgb::QueueHeader*>(base);
+    slot.ws.heads = reinterpret_cast<int32_t*>(base + 1024);
+    slot.ws.blocks = reinterpret_cast<int32_t*>(base + blocks_off);
+    slot.ws.order = reinterpret_cast<int32_t*>(base + order_off);
+    slot.ws.cls = reinterpret_cast<uint8_t*>(base + cls_off);
+    return RGB_OK;
+}
+
+// Workspace of the solves issued on `stream`.
+rgb_err_t stream_workspace(rgb_ctx_t* ctx, void* stream, int64_t num_lps, rgb::Workspace& out) {
     WsSlot* slot = nullptr;
     for (auto& s : ctx->slots)
         if (s.stream == stream) slot = &s;
@@ -94,41 +154,95 @@ rgb_err_t get_workspace(rgb_ctx_t* ctx, void* stream, int64_t num_lps, rgb::Work
         slot = &ctx->slots.back();
         slot->stream = stream;
     }
-    if (slot->cap < num_lps || !slot->mem) {
-        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-        if (hipStreamIsCapturing(reinterpret_cast<hipStream_t>(stream), &cs) == hipSuccess &&
-            cs != hipStreamCaptureStatusNone)
-            return fail(ctx, RGB_ERR_INVALID_ARG, "workspace must grow but the stream is being captured");
-        int64_t cap = num_lps < 1024 ? 1024 : num_lps + num_lps / 4;
-        static_assert(sizeof(rgb::QueueHeader) <= 1024, "queue header");
-        static_assert(rgb::kQueues * rgb::kHeadStride * 4 <= 1024, "queue heads");
-        size_t head_bytes = 2048;
-        size_t blocks_off = head_bytes;
-        size_t order_off = blocks_off + (size_t)rgb::kBinBlocks * rgb::kClasses * 4;
-        size_t cls_off = align_up(order_off + (size_t)cap * 4, 256);
-        size_t total = cls_off + align_up((size_t)cap, 256);
-        if (slot->mem) {
-            (void)hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream));
-            (void)hipFree(slot->mem);
-            slot->mem = nullptr;
-            slot->cap = 0;
-        }
-        void* mem = nullptr;
-        if (hipMalloc(&mem, total) != hipSuccess) return fail(ctx, RGB_ERR_OOM, "workspace of %zu bytes", total);
-        if (hipMemset(mem, 0, head_bytes) != hipSuccess) {
-            (void)hipFree(mem);
-            return fail(ctx, RGB_ERR_DEVICE, "workspace init failed");
-        }
-        char* base = static_cast<char*>(mem);
-        slot->mem = mem;
-        slot->cap = cap;
-        slot->ws.q = reinterpret_cast<rgb::QueueHeader*>(base);
-        slot->ws.heads = reinterpret_cast<int32_t*>(base + 1024);
-        slot->ws.blocks = reinterpret_cast<int32_t*>(base + blocks_off);
-        slot->ws.order = reinterpret_cast<int32_t*>(base + order_off);
-        slot->ws.cls = reinterpret_cast<uint8_t*>(base + cls_off);
-    }
+    rgb_err_t rc = grow_workspace(ctx, *slot, num_lps);
+    if (rc != RGB_OK) return rc;
     out = slot->ws;
+    return RGB_OK;
+}
+
+struct Batch {
+    int64_t num_lps, num_constraints;
+    const int64_t* offsets;
+    const float *ax, *ay, *b, *cx, *cy;
+    float *x_out, *y_out;
+    int32_t* status_out;
+};
+
+rgb_err_t check_batch(rgb_ctx_t* ctx, const Batch& B) {
+    if (B.num_lps < 0 || B.num_constraints < 0)
+        return fail(ctx, RGB_ERR_INVALID_ARG, "negative num_lps (%lld) or num_constraints (%lld)",
+                    (long long)B.num_lps, (long long)B.num_constraints);
+    if (B.num_lps == 0) return RGB_OK;
+    if (!B.offsets || !B.cx || !B.cy || !B.x_out || !B.y_out || !B.status_out)
+        return fail(ctx, RGB_ERR_INVALID_ARG, "null per-LP pointer");
+    if (B.num_constraints > 0 && (!B.ax || !B.ay || !B.b)) return fail(ctx, RGB_ERR_INVALID_ARG, "null row pointer");
+    if (B.num_lps > (int64_t)0x7fffffff - rgb::kClasses)
+        return fail(ctx, RGB_ERR_TOO_LARGE, "num_lps above 2^31 - 17");
+    return RGB_OK;
+}
+
+rgb::Problem make_problem(const Batch& B, int32_t* n1d) {
+    rgb::Problem P{};
+    P.offsets = B.offsets;
+    P.ax = B.ax;
+    P.ay = B.ay;
+    P.b = B.b;
+    P.cx = B.cx;
+    P.cy = B.cy;
+    P.x_out = B.x_out;
+    P.y_out = B.y_out;
+    P.status = B.status_out;
+    P.n1d = n1d;
+    P.order = nullptr;
+    P.num_lps = B.num_lps;
+    P.num_constraints = B.num_constraints;
+    return P;
+}
+
+// Effective configuration of a call: ctx's tuning with the opts overrides.
+rgb_err_t resolve(rgb_ctx_t* ctx, const rgb_solve_opts_t& o, int& variant, rgb_tuning_t& cfg) {
+    cfg = ctx->tuning;
+    variant = o.variant;
+    if (variant < RGB_VARIANT_AUTO || variant > RGB_VARIANT_BINNED)
+        return fail(ctx, RGB_ERR_INVALID_ARG, "unknown variant %d", variant);
+    if (o.slots != 0) return fail(ctx, RGB_ERR_INVALID_ARG, "opts.slots is reserved and must be 0");
+    if (variant == RGB_VARIANT_AUTO) variant = cfg.variant;
+    if (o.lanes_per_lp) {
+        if (!lanes_ok(o.lanes_per_lp))
+            return fail(ctx, RGB_ERR_INVALID_ARG, "lanes_per_lp=%d is not one of 4, 8, 16, 32, 64", o.lanes_per_lp);
+        cfg.batched_lanes = o.lanes_per_lp;
+        for (int c = 0; c < rgb::kClasses; ++c) cfg.log2_lanes[c] = __builtin_ctz(o.lanes_per_lp);
+    }
+    if (o.chunk < 0 || o.grid < 0) return fail(ctx, RGB_ERR_INVALID_ARG, "negative chunk or grid");
+    if (o.chunk) cfg.chunk = o.chunk;
+    if (o.grid) cfg.grid = o.grid;
+    if (o.queue_share < -1 || o.queue_share > 1024)
+        return fail(ctx, RGB_ERR_INVALID_ARG, "queue_share %d outside [-1, 1024]", o.queue_share);
+    if (o.queue_share) cfg.queue_share = o.queue_share < 0 ? 0 : o.queue_share;
+    return RGB_OK;
+}
+
+// Enqueue one solve.  W is needed by PERSISTENT and BINNED only.
+rgb_err_t enqueue(rgb_ctx_t* ctx, const rgb::Problem& P, int variant, const rgb_tuning_t& cfg,
+                  const rgb::Workspace* W, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+    hipError_t e;
+    if (variant == RGB_VARIANT_PLAIN) {
+        if (ev0) (void)hipEventRecord(ev0, st);
+        e = rgb::launch_plain(P, st);
+        if (ev1) (void)hipEventRecord(ev1, st);
+    } else if (variant == RGB_VARIANT_BATCHED) {
+        if (ev0) (void)hipEventRecord(ev0, st);
+        e = rgb::launch_group(P, cfg.batched_lanes, st);
+        if (ev1) (void)hipEventRecord(ev1, st);
+    } else {
+        rgb::PersistPlan plan{};
+        for (int c = 0; c < rgb::kClasses; ++c) plan.log2_lanes[c] = cfg.log2_lanes[c];
+        plan.dyn_frac_1024 = cfg.queue_share;
+        plan.chunk = cfg.chunk;
+        int grid = cfg.grid ? cfg.grid : ctx->num_cus * ctx->persist_blocks_per_cu;
+        e = rgb::launch_persistent(P, *W, plan, grid, variant == RGB_VARIANT_BINNED, st, ev0, ev1);
+    }
+    if (e != hipSuccess) return fail(ctx, RGB_ERR_DEVICE, "launch failed: %s", hipGetErrorString(e));
     return RGB_OK;
 }
 
@@ -136,7 +250,7 @@ rgb_err_t get_workspace(rgb_ctx_t* ctx, void* stream, int64_t num_lps, rgb::Work
 
 extern "C" {
 
-const char* rgb_version(void) { return "rgb-mi355x 0.1 (gfx950)"; }
+const char* rgb_version(void) { return "rgb-mi355x 0.2 (gfx950)"; }
 
 rgb_err_t rgb_ctx_create(int device, rgb_ctx_t** out) {
     if (!out) return RGB_ERR_INVALID_ARG;
@@ -155,7 +269,7 @@ rgb_err_t rgb_ctx_create(int device, rgb_ctx_t** out) {
     }
     ctx->num_cus = prop.multiProcessorCount;
     ctx->persist_blocks_per_cu = rgb::persist_blocks_per_cu();
-    default_plan(ctx->plan);
+    default_tuning(ctx->tuning);
     *out = ctx;
     return RGB_OK;
 }
@@ -176,80 +290,240 @@ const char* rgb_ctx_last_error(const rgb_ctx_t* ctx) {
     return ctx->last_error.c_str();
 }
 
+rgb_err_t rgb_ctx_get_tuning(const rgb_ctx_t* ctx, rgb_tuning_t* out) {
+    if (!ctx || !out) return RGB_ERR_INVALID_ARG;
+    *out = ctx->tuning;
+    return RGB_OK;
+}
+
+rgb_err_t rgb_ctx_set_tuning(rgb_ctx_t* ctx, const rgb_tuning_t* tuning) {
+    if (!ctx || !tuning) return RGB_ERR_INVALID_ARG;
+    if (!tuning_valid(*tuning)) return fail(ctx, RGB_ERR_INVALID_ARG, "invalid tuning");
+    ctx->tuning = *tuning;
+    return RGB_OK;
+}
+
 rgb_err_t rgb_solve_batch(rgb_ctx_t* ctx, int64_t num_lps, int64_t num_constraints, const int64_t* offsets,
                           const float* ax, const float* ay, const float* b, const float* cx, const float* cy,
                           float* x_out, float* y_out, int32_t* status_out, const rgb_solve_opts_t* opts,
                           void* stream) {
     if (!ctx) return RGB_ERR_INVALID_ARG;
     ctx->last_error.clear();
-    if (num_lps < 0 || num_constraints < 0)
-        return fail(ctx, RGB_ERR_INVALID_ARG, "negative num_lps (%lld) or num_constraints (%lld)",
-                    (long long)num_lps, (long long)num_constraints);
-    if (num_lps == 0) return RGB_OK;
-    if (!offsets || !cx || !cy || !x_out || !y_out || !status_out)
-        return fail(ctx, RGB_ERR_INVALID_ARG, "null per-LP pointer");
-    if (num_constraints > 0 && (!ax || !ay || !b)) return fail(ctx, RGB_ERR_INVALID_ARG, "null row pointer");
-    if (num_lps > (int64_t)0x7fffffff) return fail(ctx, RGB_ERR_TOO_LARGE, "num_lps above 2^31-1");
-
+    Batch B{num_lps, num_constraints, offsets, ax, ay, b, cx, cy, x_out, y_out, status_out};
+    rgb_err_t rc = check_batch(ctx, B);
+    if (rc != RGB_OK || num_lps == 0) return rc;
     rgb_solve_opts_t o{};
     if (opts) o = *opts;
-    int variant = o.variant;
-    if (variant < RGB_VARIANT_AUTO || variant > RGB_VARIANT_BINNED)
-        return fail(ctx, RGB_ERR_INVALID_ARG, "unknown variant %d", variant);
+    int variant;
+    rgb_tuning_t cfg;
+    if ((rc = resolve(ctx, o, variant, cfg)) != RGB_OK) return rc;
+    DeviceGuard guard(ctx->device);
+    if (!guard.ok) return fail(ctx, RGB_ERR_DEVICE, "cannot select device %d", ctx->device);
+    rgb::Workspace W{};
+    if (variant == RGB_VARIANT_PERSISTENT || variant == RGB_VARIANT_BINNED)
+        if ((rc = stream_workspace(ctx, stream, num_lps, W)) != RGB_OK) return rc;
+    return enqueue(ctx, make_problem(B, o.n_1dlp_out), variant, cfg, &W, reinterpret_cast<hipStream_t>(stream),
+                   reinterpret_cast<hipEvent_t>(o.ev_begin), reinterpret_cast<hipEvent_t>(o.ev_end));
+}
 
-    rgb::Problem P{};
-    P.offsets = offsets;
-    P.ax = ax;
-    P.ay = ay;
-    P.b = b;
-    P.cx = cx;
-    P.cy = cy;
-    P.x_out = x_out;
-    P.y_out = y_out;
-    P.status = status_out;
-    P.n1d = o.n_1dlp_out;
-    P.order = nullptr;
-    P.num_lps = num_lps;
-    P.num_constraints = num_constraints;
-
+rgb_err_t rgb_autotune(rgb_ctx_t* ctx, int64_t num_lps, int64_t num_constraints, const int64_t* offsets,
+                       const float* ax, const float* ay, const float* b, const float* cx, const float* cy,
+                       float* x_out, float* y_out, int32_t* status_out, int32_t reps, double budget_ms,
+                       void* stream, rgb_tuning_t* best) {
+    if (!ctx) return RGB_ERR_INVALID_ARG;
+    ctx->last_error.clear();
+    Batch B{num_lps, num_constraints, offsets, ax, ay, b, cx, cy, x_out, y_out, status_out};
+    rgb_err_t rc = check_batch(ctx, B);
+    if (rc != RGB_OK) return rc;
+    if (reps < 1 || reps > 1000) return fail(ctx, RGB_ERR_INVALID_ARG, "reps %d outside [1, 1000]", reps);
+    if (num_lps == 0) {
+        if (best) *best = ctx->tuning;
+        return RGB_OK;
+    }
     DeviceGuard guard(ctx->device);
     if (!guard.ok) return fail(ctx, RGB_ERR_DEVICE, "cannot select device %d", ctx->device);
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    hipError_t e;
-    if (o.slots != 0) return fail(ctx, RGB_ERR_INVALID_ARG, "opts.slots is reserved and must be 0");
-    hipEvent_t ev0 = reinterpret_cast<hipEvent_t>(o.ev_begin), ev1 = reinterpret_cast<hipEvent_t>(o.ev_end);
-    if (variant == RGB_VARIANT_PLAIN) {
-        if (ev0) (void)hipEventRecord(ev0, st);
-        e = rgb::launch_plain(P, st);
-        if (ev1) (void)hipEventRecord(ev1, st);
-    } else if (variant == RGB_VARIANT_AUTO || variant == RGB_VARIANT_PERSISTENT || variant == RGB_VARIANT_BINNED) {
-        if (o.chunk < 0 || o.grid < 0) return fail(ctx, RGB_ERR_INVALID_ARG, "negative chunk or grid");
-        rgb::Workspace W;
-        rgb_err_t rc = get_workspace(ctx, stream, num_lps, W);
-        if (rc != RGB_OK) return rc;
-        rgb::PersistPlan plan = ctx->plan;
-        if (o.chunk) plan.chunk = o.chunk;
-        if (o.queue_share < -1 || o.queue_share > 1024)
-            return fail(ctx, RGB_ERR_INVALID_ARG, "queue_share %d outside [-1, 1024]", o.queue_share);
-        if (o.queue_share) plan.dyn_frac_1024 = o.queue_share < 0 ? 0 : o.queue_share;
-        if (o.lanes_per_lp) {
-            if (!rgb::group_supported(o.lanes_per_lp))
-                return fail(ctx, RGB_ERR_INVALID_ARG, "lanes_per_lp=%d is not one of 4, 8, 16, 32, 64", o.lanes_per_lp);
-            for (int c = 0; c < rgb::kClasses; ++c) plan.log2_lanes[c] = __builtin_ctz(o.lanes_per_lp);
-        }
-        int grid = o.grid ? o.grid : ctx->num_cus * ctx->persist_blocks_per_cu;
-        bool binned = variant == RGB_VARIANT_BINNED;
-        e = rgb::launch_persistent(P, W, plan, grid, binned, st, reinterpret_cast<hipEvent_t>(o.ev_begin),
-                                   reinterpret_cast<hipEvent_t>(o.ev_end));
-    } else {
-        int g = o.lanes_per_lp ? o.lanes_per_lp : kDefaultLanes;
-        if (!rgb::group_supported(g))
-            return fail(ctx, RGB_ERR_INVALID_ARG, "lanes_per_lp=%d is not one of 4, 8, 16, 32, 64", g);
-        if (ev0) (void)hipEventRecord(ev0, st);
-        e = rgb::launch_group(P, g, st);
-        if (ev1) (void)hipEventRecord(ev1, st);
+    rgb::Workspace W{};
+    if ((rc = stream_workspace(ctx, stream, num_lps, W)) != RGB_OK) return rc;
+    const rgb::Problem P = make_problem(B, nullptr);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        return fail(ctx, RGB_ERR_DEVICE, "event create failed");
     }
-    if (e != hipSuccess) return fail(ctx, RGB_ERR_DEVICE, "launch failed: %s", hipGetErrorString(e));
+    const auto t_start = std::chrono::steady_clock::now();
+    auto elapsed_ms = [&] {
+        return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+    };
+    // median time of `reps` whole solves (binning included) with cfg
+    auto measure = [&](const rgb_tuning_t& cfg, float& ms) -> rgb_err_t {
+        std::vector<float> t;
+        rgb_err_t r = enqueue(ctx, P, cfg.variant, cfg, &W, st, nullptr, nullptr);  // warm-up
+        if (r != RGB_OK) return r;
+        for (int i = 0; i < reps; ++i) {
+            (void)hipEventRecord(e0, st);
+            if ((r = enqueue(ctx, P, cfg.variant, cfg, &W, st, nullptr, nullptr)) != RGB_OK) return r;
+            (void)hipEventRecord(e1, st);
+            if (hipEventSynchronize(e1) != hipSuccess) return fail(ctx, RGB_ERR_DEVICE, "solve failed");
+            float v = 0.0f;
+            (void)hipEventElapsedTime(&v, e0, e1);
+            t.push_back(v);
+        }
+        std::sort(t.begin(), t.end());
+        ms = t[t.size() / 2];
+        return RGB_OK;
+    };
+    rgb_tuning_t win = ctx->tuning;
+    win.ms = 1e30f;
+    auto try_cfg = [&](rgb_tuning_t cand) -> rgb_err_t {
+        float ms = 0.0f;
+        rgb_err_t r = measure(cand, ms);
+        if (r != RGB_OK) return r;
+        cand.ms = ms;
+        if (ms < win.ms) win = cand;
+        return RGB_OK;
+    };
+    auto tune = [&]() -> rgb_err_t {
+        const rgb_tuning_t cur = ctx->tuning;
+        rgb_err_t r;
+        // 1. the kernel families with their default shapes, BATCHED at every width
+        for (int v : {RGB_VARIANT_PERSISTENT, RGB_VARIANT_BINNED}) {
+            rgb_tuning_t c = cur;
+            c.variant = v;
+            if ((r = try_cfg(c)) != RGB_OK) return r;
+        }
+        for (int g : {8, 16, 32, 64}) {
+            rgb_tuning_t c = cur;
+            c.variant = RGB_VARIANT_BATCHED;
+            c.batched_lanes = g;
+            if ((r = try_cfg(c)) != RGB_OK) return r;
+        }
+        // 2. rows per size class, from a binning pass
+        std::vector<uint8_t> cls((size_t)num_lps);
+        std::vector<int64_t> offs((size_t)num_lps + 1);
+        {
+            rgb_tuning_t c = cur;
+            c.variant = RGB_VARIANT_BINNED;
+            if ((r = enqueue(ctx, P, c.variant, c, &W, st, nullptr, nullptr)) != RGB_OK) return r;
+        }
+        if (hipStreamSynchronize(st) != hipSuccess ||
+            hipMemcpy(cls.data(), W.cls, (size_t)num_lps, hipMemcpyDeviceToHost) != hipSuccess ||
+            hipMemcpy(offs.data(), offsets, offs.size() * 8, hipMemcpyDeviceToHost) != hipSuccess)
+            return fail(ctx, RGB_ERR_DEVICE, "reading the size classes failed");
+        int64_t rows[rgb::kClasses] = {0}, total = 0;
+        for (int64_t k = 0; k < num_lps; ++k) {
+            int64_t m = offs[k + 1] - offs[k];
+            if (m < 0) m = 0;
+            rows[cls[k] & (rgb::kClasses - 1)] += m;
+            total += m;
+        }
+        // 3. lanes per LP, class by class (largest share of rows first), for both binned families
+        std::vector<int> order;
+        for (int c = 0; c < rgb::kClasses; ++c)
+            if (total > 0 && rows[c] * 25 >= total) order.push_back(c);
+        std::sort(order.begin(), order.end(), [&](int a, int bb) { return rows[a] > rows[bb]; });
+        rgb_tuning_t base = win;
+        if (base.variant == RGB_VARIANT_BATCHED) {
+            base = cur;
+            base.variant = RGB_VARIANT_PERSISTENT;
+        }
+        for (int c : order) {
+            if (elapsed_ms() > budget_ms) break;
+            for (int v : {RGB_VARIANT_PERSISTENT, RGB_VARIANT_BINNED})
+                for (int lg = 2; lg <= 6; ++lg) {
+                    rgb_tuning_t cand = base;
+                    cand.variant = v;
+                    cand.log2_lanes[c] = lg;
+                    if ((r = try_cfg(cand)) != RGB_OK) return r;
+                }
+            if (win.variant != RGB_VARIANT_BATCHED) base = win;
+        }
+        // 4. queue share and chunk of the persistent kernel
+        for (int share : {0, 128, 512, 1024})
+            for (int chunk : {1, 2, 4}) {
+                if (elapsed_ms() > budget_ms) return RGB_OK;
+                if (share == 0 && chunk > 1) continue;
+                rgb_tuning_t cand = base;
+                cand.variant = RGB_VARIANT_PERSISTENT;
+                cand.queue_share = share;
+                cand.chunk = chunk;
+                if ((r = try_cfg(cand)) != RGB_OK) return r;
+            }
+        return RGB_OK;
+    };
+    rc = tune();
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != RGB_OK) return rc;
+    ctx->tuning = win;
+    if (best) *best = win;
+    return RGB_OK;
+}
+
+rgb_err_t rgb_plan_create(rgb_ctx_t* ctx, int64_t num_lps, int64_t num_constraints, const int64_t* offsets,
+                          const float* ax, const float* ay, const float* b, const float* cx, const float* cy,
+                          float* x_out, float* y_out, int32_t* status_out, const rgb_solve_opts_t* opts,
+                          rgb_plan_t** out) {
+    if (!ctx || !out) return RGB_ERR_INVALID_ARG;
+    *out = nullptr;
+    ctx->last_error.clear();
+    Batch B{num_lps, num_constraints, offsets, ax, ay, b, cx, cy, x_out, y_out, status_out};
+    rgb_err_t rc = check_batch(ctx, B);
+    if (rc != RGB_OK) return rc;
+    rgb_solve_opts_t o{};
+    if (opts) o = *opts;
+    int variant;
+    rgb_tuning_t cfg;
+    if ((rc = resolve(ctx, o, variant, cfg)) != RGB_OK) return rc;
+    DeviceGuard guard(ctx->device);
+    if (!guard.ok) return fail(ctx, RGB_ERR_DEVICE, "cannot select device %d", ctx->device);
+    rgb_plan_t* plan = new (std::nothrow) rgb_plan_t();
+    if (!plan) return fail(ctx, RGB_ERR_OOM, "plan");
+    plan->ctx = ctx;
+    if ((rc = grow_workspace(ctx, plan->ws, num_lps)) != RGB_OK) {
+        delete plan;
+        return rc;
+    }
+    hipStream_t cap;
+    if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) {
+        rgb_plan_destroy(plan);
+        return fail(ctx, RGB_ERR_DEVICE, "stream create failed");
+    }
+    hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        if (num_lps > 0)
+            rc = enqueue(ctx, make_problem(B, o.n_1dlp_out), variant, cfg, &plan->ws.ws, cap,
+                         reinterpret_cast<hipEvent_t>(o.ev_begin), reinterpret_cast<hipEvent_t>(o.ev_end));
+        e = hipStreamEndCapture(cap, &plan->graph);
+    }
+    (void)hipStreamDestroy(cap);
+    if (rc != RGB_OK || e != hipSuccess) {
+        rgb_plan_destroy(plan);
+        return rc != RGB_OK ? rc : fail(ctx, RGB_ERR_DEVICE, "capture failed: %s", hipGetErrorString(e));
+    }
+    if ((e = hipGraphInstantiate(&plan->exec, plan->graph, nullptr, nullptr, 0)) != hipSuccess) {
+        rgb_plan_destroy(plan);
+        return fail(ctx, RGB_ERR_DEVICE, "graph instantiate failed: %s", hipGetErrorString(e));
+    }
+    *out = plan;
+    return RGB_OK;
+}
+
+rgb_err_t rgb_plan_launch(rgb_plan_t* plan, void* stream) {
+    if (!plan || !plan->exec) return RGB_ERR_INVALID_ARG;
+    DeviceGuard guard(plan->ctx->device);
+    hipError_t e = hipGraphLaunch(plan->exec, reinterpret_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return fail(plan->ctx, RGB_ERR_DEVICE, "graph launch failed: %s", hipGetErrorString(e));
+    return RGB_OK;
+}
+
+rgb_err_t rgb_plan_destroy(rgb_plan_t* plan) {
+    if (!plan) return RGB_OK;
+    DeviceGuard guard(plan->ctx->device);
+    if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
+    if (plan->graph) (void)hipGraphDestroy(plan->graph);
+    if (plan->ws.mem) (void)hipFree(plan->ws.mem);
+    delete plan;
     return RGB_OK;
 }
 

@@ -20,6 +20,28 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, public spec
 
+# HBM bytes per launch of the dominant kernel, from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE passes scaled by the same counters read for a device copy of
+# known size (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0 on gfx950); see profiles/.
+# Keyed by (kernel, workload) and valid only for the kernel sources whose
+# digest is recorded: after any kernel change the figure is reported as null.
+MEASURED_TRAFFIC = {
+    "sources": "77072b5cc8653072",
+    ("k_group", "uniform"): 448753530,
+    ("k_persist", "uneven"): 9310362115,
+    ("k_group", "crowd"): 251685580,
+}
+
+
+def kernel_source_digest():
+    import hashlib
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_1902_04995_amd", "csrc")
+    for f in ("rgb_kernels.hip", "rgb_device.hpp", "rgb_internal.hpp"):
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
 WORKLOADS = {
     "uniform": "131,072 LPs x 256 half-planes (+4 box rows; 5% infeasible, 2% unbounded), FP32",
     "uneven": "200,000 LPs, half-planes log-uniform in [8, 8192] (+box; 5% infeasible, 2% unbounded), FP32",
@@ -105,6 +127,22 @@ def main():
     st = out[2].cpu().numpy()
     status_counts = np.bincount(st, minlength=4).tolist()
 
+    # achievable-bandwidth context: a device copy of as many bytes as the solve reads and writes
+    n_copy = alg_bytes // 8
+    src = torch.empty(n_copy, dtype=torch.float32, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    c0.record(stream)
+    for _ in range(5):
+        dst.copy_(src)
+    c1.record(stream)
+    torch.cuda.synchronize()
+    copy_ms = c0.elapsed_time(c1) / 5
+    copy_probe = {"bytes_moved": 8 * n_copy, "ms": copy_ms, "gbs": 8 * n_copy / (copy_ms / 1e3) / 1e9}
+    del src, dst
+
     plain = None
     if not args.no_plain:
         p_steps = max(2, min(args.steps, 5))
@@ -130,6 +168,10 @@ def main():
               file=sys.stderr, flush=True)
 
     achieved = alg_bytes / (kern_ms / 1e3) / 1e9
+    kname = kernel_name(args.variant, tuning)
+    traffic = None
+    if kernel_source_digest() == MEASURED_TRAFFIC["sources"]:
+        traffic = MEASURED_TRAFFIC.get((kname, args.workload))
     line = {
         "metric": "LPs/sec + achieved HBM GB/s, batched vs plain kernel; p50/p99 served latency",
         "value": bt.num_lps / (ms_step / 1e3),
@@ -151,9 +193,10 @@ def main():
         "plain": plain,
         "batched_over_plain": (bt.num_lps / (ms_step / 1e3)) / plain["lps_per_s"] if plain else None,
         "status_counts": status_counts,
+        "copy_probe": copy_probe,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": kernel_name(args.variant, tuning),
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": kname,
                      "algorithmic_bytes_per_launch": alg_bytes,
                      "kernel_ms_mean": kern_ms, "kernel_ms_median": kern_med},
         "cpu_baseline": cpu,

@@ -50,6 +50,59 @@ WORKLOADS = {
 }
 
 
+def served_leg(rgb, gen, n_requests, load, pool_size=96, seed=0):
+    """Poisson stream of requests (1..4096 LPs, 16..2048 rows each, same mix)
+    at `load` x the capacity measured with a burst, through (a) the
+    continuous-batching server and (b) a FIFO server that solves one request
+    at a time with the plain kernel, on the same arrival trace.  Latency =
+    completion - scheduled arrival."""
+    import numpy as np
+
+    rng = gen.rng_for(5, seed)
+    pool = [gen.served_request(rng) for _ in range(pool_size)]
+    lps = np.array([r.num_lps for r in pool])
+
+    def run(srv, order, arrivals):
+        tickets = []
+        t0 = time.perf_counter()
+        for k, t_arr in zip(order, arrivals):
+            while time.perf_counter() - t0 < t_arr:
+                pass
+            t_sub = time.perf_counter() - t0
+            tickets.append((srv.submit(pool[k]), t_sub - t_arr, k))
+        lat = []
+        for t, lag, k in tickets:
+            _, _, _, ms = srv.wait(t)
+            lat.append(ms + 1e3 * lag)
+        wall = time.perf_counter() - t0
+        total = int(sum(lps[k] for _, _, k in tickets))
+        lat = np.array(lat)
+        return {"requests": len(tickets), "lps": total, "wall_s": wall, "lps_per_s": total / wall,
+                "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                "max_ms": float(lat.max())}
+
+    served = rgb.Server(n_streams=4, max_batch_lps=16384, hbm_budget=4 << 30)
+    fifo = rgb.Server(n_streams=1, one_request_per_batch=True, variant="plain", hbm_budget=4 << 30)
+    # warm-up (pinned buffers, workspaces) and capacity from a burst of the whole pool
+    for srv in (served, fifo):
+        for t in [srv.submit(r) for r in pool[:8]]:
+            srv.wait(t)
+    t0 = time.perf_counter()
+    for t in [served.submit(r) for r in pool]:
+        served.wait(t)
+    capacity = float(lps.sum()) / (time.perf_counter() - t0)
+    order = rng.integers(0, pool_size, n_requests)
+    rate = load * capacity / float(lps.mean())  # requests per second
+    arrivals = gen.poisson_arrivals(rng, n_requests, rate)
+    out = {"capacity_lps_per_s": capacity, "offered_load": load, "offered_lps_per_s": load * capacity,
+           "request_mix": "n ~ floor(logU[1, 4096]) LPs, m ~ logU[16, 2048] + box rows, 5% infeasible, 2% unbounded",
+           "served": run(served, order, arrivals), "plain_fifo": run(fifo, order, arrivals)}
+    out["served"]["stats"] = served.stats()
+    served.close()
+    fifo.close()
+    return out
+
+
 def kernel_name(variant, tuning):
     v = tuning["variant"] if (variant == "auto" and tuning) else variant
     v = "persistent" if v == "auto" else v
@@ -68,6 +121,8 @@ def main():
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-kernel comparison")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (AUTO uses the default plan)")
     ap.add_argument("--tune-budget-ms", type=float, default=3000.0)
+    ap.add_argument("--served-requests", type=int, default=1500, help="0 skips the served leg")
+    ap.add_argument("--served-load", type=float, default=0.7)
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -151,6 +206,12 @@ def main():
                  "hbm_gbs": alg_bytes / (p_kern / 1e3) / 1e9, "steps": p_steps}
         print(f"[bench] plain: {p_ms:.3f} ms/step", file=sys.stderr, flush=True)
 
+    served = None
+    if args.served_requests > 0:
+        served = served_leg(rgb, gen, args.served_requests, args.served_load)
+        print(f"[bench] served: {json.dumps({k: v for k, v in served.items() if k in ('served', 'plain_fifo')})}",
+              file=sys.stderr, flush=True)
+
     cpu = None
     if not args.no_cpu:
         import oracle
@@ -200,6 +261,7 @@ def main():
                      "algorithmic_bytes_per_launch": alg_bytes,
                      "kernel_ms_mean": kern_ms, "kernel_ms_median": kern_med},
         "cpu_baseline": cpu,
+        "served": served,
     }
     print(json.dumps(line))
 

@@ -176,6 +176,67 @@ rgb_err_t rgb_plan_create(rgb_ctx_t* ctx, int64_t num_lps, int64_t num_constrain
 rgb_err_t rgb_plan_launch(rgb_plan_t* plan, void* stream);
 rgb_err_t rgb_plan_destroy(rgb_plan_t* plan);
 
+/* ---------------------------------------------------------------------------
+ * Served mode: continuous batching of LP requests.
+ *
+ * A server owns a device arena of `hbm_budget` bytes, its own context (with
+ * the creating context's tuning), `n_streams` streams and one scheduler
+ * thread.  Requests are submitted from host memory and queued; the scheduler
+ * admits them in arrival order into micro-batches as soon as a stream is free
+ * and the arena has room (a request that arrives while others are on the GPU
+ * joins the next micro-batch, and micro-batches on different streams overlap
+ * on the device), copies each micro-batch through pinned memory into the
+ * arena, solves it with rgb_solve_batch, copies the results back and frees
+ * the arena block.  Results are exactly those of solving each request alone.
+ * All calls are thread-safe.
+ * ------------------------------------------------------------------------- */
+typedef struct rgb_server rgb_server_t;
+
+typedef struct {
+    uint64_t hbm_budget;           /* device bytes for request data; 0 = 1 GiB */
+    int32_t n_streams;             /* micro-batches in flight at once, 1..16; 0 = 4 */
+    int32_t max_batch_lps;         /* LPs per micro-batch at most; 0 = 65536 */
+    int32_t max_pending;           /* queued, not yet admitted requests; 0 = 65536 */
+    int32_t variant;               /* kernel family of the micro-batches; AUTO = the tuning */
+    int32_t one_request_per_batch; /* 1: every micro-batch holds a single request (no batching) */
+    int32_t reserved;
+} rgb_server_opts_t;
+
+typedef struct {
+    uint64_t submitted, completed, rejected_busy, rejected_too_large;
+    uint64_t lps_completed, micro_batches;
+    uint64_t arena_bytes_in_use, arena_bytes_peak;
+    int32_t pending, in_flight;    /* requests queued / admitted and not yet finished */
+} rgb_server_stats_t;
+
+/* Start a server on ctx's device (ctx itself is not used afterwards).
+ * Errors: INVALID_ARG (bad option), OOM (arena or pinned buffers), DEVICE. */
+rgb_err_t rgb_server_create(rgb_ctx_t* ctx, const rgb_server_opts_t* opts, rgb_server_t** out);
+
+/* Queue one request.  Pointers are HOST memory in the layout of
+ * rgb_solve_batch and are copied before the call returns.  *ticket receives
+ * the request's id.  Errors: INVALID_ARG; TOO_LARGE if the request can never
+ * fit (more LPs than max_batch_lps, or more bytes than the arena);
+ * BUSY if max_pending requests are already queued (retry later). */
+rgb_err_t rgb_server_submit(rgb_server_t* srv, int64_t num_lps, int64_t num_constraints, const int64_t* offsets,
+                            const float* ax, const float* ay, const float* b, const float* cx, const float* cy,
+                            uint64_t* ticket);
+
+/* Wait up to wait_ms (-1: forever, 0: just look) for request `ticket`.  When
+ * it is done, *done = 1, the results are copied to the HOST arrays x_out,
+ * y_out, status_out (num_lps each), *latency_ms (may be NULL) receives the
+ * time from submission to completion, and the ticket is released.
+ * Otherwise *done = 0.  Errors: NOT_FOUND (unknown or released ticket),
+ * DEVICE (the micro-batch of this request failed). */
+rgb_err_t rgb_server_poll(rgb_server_t* srv, uint64_t ticket, int32_t wait_ms, float* x_out, float* y_out,
+                          int32_t* status_out, double* latency_ms, int32_t* done);
+
+rgb_err_t rgb_server_stats(rgb_server_t* srv, rgb_server_stats_t* out);
+
+/* Stop the scheduler after the admitted micro-batches finish and free
+ * everything; requests not yet admitted are dropped.  NULL is a no-op. */
+rgb_err_t rgb_server_destroy(rgb_server_t* srv);
+
 #ifdef __cplusplus
 }
 #endif

@@ -63,6 +63,19 @@ class Tuning(ctypes.Structure):
         return t
 
 
+class _ServerOpts(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_uint64), ("n_streams", ctypes.c_int32), ("max_batch_lps", ctypes.c_int32),
+                ("max_pending", ctypes.c_int32), ("variant", ctypes.c_int32), ("one_request_per_batch", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class _ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64), ("rejected_busy", ctypes.c_uint64),
+                ("rejected_too_large", ctypes.c_uint64), ("lps_completed", ctypes.c_uint64),
+                ("micro_batches", ctypes.c_uint64), ("arena_bytes_in_use", ctypes.c_uint64),
+                ("arena_bytes_peak", ctypes.c_uint64), ("pending", ctypes.c_int32), ("in_flight", ctypes.c_int32)]
+
+
 def lib():
     """Load librgb.so (after torch, so both use one HIP runtime)."""
     global _lib
@@ -97,6 +110,17 @@ def lib():
         L.rgb_plan_launch.restype = I32
         L.rgb_plan_destroy.argtypes = [P]
         L.rgb_plan_destroy.restype = I32
+        L.rgb_server_create.argtypes = [P, ctypes.POINTER(_ServerOpts), ctypes.POINTER(P)]
+        L.rgb_server_create.restype = I32
+        L.rgb_server_submit.argtypes = [P, I64, I64] + [P] * 6 + [ctypes.POINTER(ctypes.c_uint64)]
+        L.rgb_server_submit.restype = I32
+        L.rgb_server_poll.argtypes = [P, ctypes.c_uint64, I32, P, P, P, ctypes.POINTER(ctypes.c_double),
+                                      ctypes.POINTER(I32)]
+        L.rgb_server_poll.restype = I32
+        L.rgb_server_stats.argtypes = [P, ctypes.POINTER(_ServerStats)]
+        L.rgb_server_stats.restype = I32
+        L.rgb_server_destroy.argtypes = [P]
+        L.rgb_server_destroy.restype = I32
         _lib = L
     return _lib
 
@@ -286,6 +310,99 @@ class Plan:
     def close(self):
         if getattr(self, "handle", None):
             lib().rgb_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+ERR_BUSY, ERR_TOO_LARGE, ERR_NOT_FOUND = -4, -5, -6
+
+
+class ServerBusy(RgbError):
+    pass
+
+
+class RequestTooLarge(RgbError):
+    pass
+
+
+class Server:
+    """Continuous-batching LP server (rgb_server_*): requests come from host
+    memory (numpy arrays), results go back to host memory."""
+
+    def __init__(self, ctx: Context | None = None, *, hbm_budget=0, n_streams=0, max_batch_lps=0, max_pending=0,
+                 variant="auto", one_request_per_batch=False):
+        self.ctx = ctx or context(0)
+        o = _ServerOpts()
+        o.hbm_budget = int(hbm_budget)
+        o.n_streams = int(n_streams)
+        o.max_batch_lps = int(max_batch_lps)
+        o.max_pending = int(max_pending)
+        o.variant = VARIANTS[variant] if isinstance(variant, str) else int(variant)
+        o.one_request_per_batch = 1 if one_request_per_batch else 0
+        h = ctypes.c_void_p()
+        rc = lib().rgb_server_create(self.ctx.handle, ctypes.byref(o), ctypes.byref(h))
+        if rc != 0:
+            raise RgbError(f"rgb_server_create failed ({rc})")
+        self.handle = h
+        self._sizes = {}
+
+    def submit(self, batch) -> int:
+        """Queue a gen.Batch-like request; returns its ticket."""
+        import numpy as np
+        arrs = [np.ascontiguousarray(batch.offsets, dtype=np.int64)] + \
+               [np.ascontiguousarray(getattr(batch, f), dtype=np.float32) for f in ("ax", "ay", "b", "cx", "cy")]
+        B = arrs[0].shape[0] - 1
+        N = arrs[1].shape[0]
+        t = ctypes.c_uint64()
+        rc = lib().rgb_server_submit(self.handle, B, N, *[ctypes.c_void_p(a.ctypes.data) for a in arrs], ctypes.byref(t))
+        if rc == ERR_BUSY:
+            raise ServerBusy("server queue full")
+        if rc == ERR_TOO_LARGE:
+            raise RequestTooLarge(f"request of {B} LPs / {N} rows can never fit")
+        if rc != 0:
+            raise RgbError(f"rgb_server_submit failed ({rc})")
+        self._sizes[t.value] = B
+        return t.value
+
+    def poll(self, ticket: int, wait_ms: int = 0):
+        """None if not done yet, else (x, y, status, latency_ms) as numpy arrays."""
+        import numpy as np
+        B = self._sizes.get(ticket)
+        if B is None:
+            raise RgbError(f"unknown ticket {ticket}")
+        x = np.empty(B, np.float32)
+        y = np.empty(B, np.float32)
+        st = np.empty(B, np.int32)
+        lat = ctypes.c_double()
+        done = ctypes.c_int32()
+        rc = lib().rgb_server_poll(self.handle, ctypes.c_uint64(ticket), int(wait_ms), ctypes.c_void_p(x.ctypes.data),
+                                   ctypes.c_void_p(y.ctypes.data), ctypes.c_void_p(st.ctypes.data), ctypes.byref(lat),
+                                   ctypes.byref(done))
+        if rc != 0:
+            raise RgbError(f"rgb_server_poll failed ({rc})")
+        if not done.value:
+            return None
+        del self._sizes[ticket]
+        return x, y, st, lat.value
+
+    def wait(self, ticket: int):
+        return self.poll(ticket, wait_ms=-1)
+
+    def stats(self) -> dict:
+        s = _ServerStats()
+        rc = lib().rgb_server_stats(self.handle, ctypes.byref(s))
+        if rc != 0:
+            raise RgbError(f"rgb_server_stats failed ({rc})")
+        return {f: getattr(s, f) for f, _ in _ServerStats._fields_}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().rgb_server_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

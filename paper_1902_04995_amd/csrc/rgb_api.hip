@@ -248,6 +248,8 @@ rgb_err_t enqueue(rgb_ctx_t* ctx, const rgb::Problem& P, int variant, const rgb_
 
 }  // namespace
 
+int rgb::ctx_device(const rgb_ctx* ctx) { return ctx->device; }
+
 extern "C" {
 
 const char* rgb_version(void) { return "rgb-mi355x 0.2 (gfx950)"; }

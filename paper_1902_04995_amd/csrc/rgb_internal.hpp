@@ -7,6 +7,8 @@
 
 #include "rgb_device.hpp"
 
+struct rgb_ctx;
+
 namespace rgb {
 
 constexpr int kClasses = 16;     // LP size classes: ceil(log2 m), capped
@@ -43,6 +45,9 @@ struct PersistPlan {
     int dyn_frac_1024;
     int chunk;
 };
+
+// Device of a context (for the server, which only sees the opaque type).
+int ctx_device(const struct ::rgb_ctx* ctx);
 
 hipError_t launch_persistent(const Problem& P, const Workspace& W, const PersistPlan& plan, int grid, bool binned,
                              hipStream_t stream, hipEvent_t ev_begin, hipEvent_t ev_end);

@@ -1,0 +1,421 @@
+// Served mode: continuous batching of LP requests over the solver ABI.
+//
+// Requests are copied in at submit time and queued.  One scheduler thread
+// owns every HIP call: it retires finished micro-batches (event polling),
+// then, for each idle stream, takes queued requests in arrival order into a
+// micro-batch while the LP cap and the arena's largest free block allow,
+// stages the micro-batch through the stream's pinned buffer into one arena
+// block, solves it with rgb_solve_batch and copies the results back.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/rgb.h"
+#include "arena.hpp"
+#include "rgb_internal.hpp"
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+enum ReqState { kQueued = 0, kAdmitted = 1, kDone = 2, kFailed = 3 };
+
+struct Request {
+    uint64_t id = 0;
+    int64_t B = 0, N = 0;
+    std::vector<int64_t> offsets;
+    std::vector<float> ax, ay, b, cx, cy;
+    std::vector<float> x, y;
+    std::vector<int32_t> st;
+    Clock::time_point t_submit, t_done;
+    int state = kQueued;
+};
+
+// Byte layout of a micro-batch of B LPs and N rows (arena block and pinned
+// staging buffer alike): inputs first (one host-to-device copy), then outputs
+// (one device-to-host copy).
+struct Layout {
+    size_t offsets, cx, cy, ax, ay, b, in_bytes, x, y, st, total;
+    static size_t al(size_t v) { return (v + 15) & ~size_t(15); }
+    Layout(int64_t B, int64_t N) {
+        size_t p = 0;
+        offsets = p; p = al(p + 8 * (size_t)(B + 1));
+        cx = p; p = al(p + 4 * (size_t)B);
+        cy = p; p = al(p + 4 * (size_t)B);
+        ax = p; p = al(p + 4 * (size_t)N);
+        ay = p; p = al(p + 4 * (size_t)N);
+        b = p; p = al(p + 4 * (size_t)N);
+        in_bytes = p;
+        x = p; p = al(p + 4 * (size_t)B);
+        y = p; p = al(p + 4 * (size_t)B);
+        st = p; p = al(p + 4 * (size_t)B);
+        total = p;
+    }
+};
+
+struct Slot {
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
+    char* pinned = nullptr;
+    size_t pinned_cap = 0;
+    bool busy = false;
+    uint64_t arena_off = 0;
+    int64_t B = 0, N = 0;
+    std::vector<Request*> reqs;
+};
+
+}  // namespace
+
+struct rgb_server {
+    int device = 0;
+    rgb_ctx_t* ctx = nullptr;
+    rgb_server_opts_t opts{};
+    char* arena_mem = nullptr;
+    rgb::Arena arena;
+    std::vector<Slot> slots;
+
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<Request*> queue;
+    std::unordered_map<uint64_t, std::unique_ptr<Request>> reqs;
+    uint64_t next_id = 1;
+    rgb_server_stats_t stats{};
+    bool stop = false;
+    std::thread thr;
+
+    void run();
+    bool retire(Slot& s);
+    bool launch(Slot& s);
+};
+
+// Finished micro-batch on slot s: copy results out, stamp, free the block.
+bool rgb_server::retire(Slot& s) {
+    hipError_t q = hipEventQuery(s.done);
+    if (q == hipErrorNotReady) return false;
+    Layout L(s.B, s.N);
+    const char* out = s.pinned;
+    std::lock_guard<std::mutex> lk(mu);
+    auto now = Clock::now();
+    int64_t k = 0;
+    for (Request* r : s.reqs) {
+        if (q == hipSuccess) {
+            std::memcpy(r->x.data(), out + L.x + 4 * k, 4 * (size_t)r->B);
+            std::memcpy(r->y.data(), out + L.y + 4 * k, 4 * (size_t)r->B);
+            std::memcpy(r->st.data(), out + L.st + 4 * k, 4 * (size_t)r->B);
+            r->state = kDone;
+            stats.lps_completed += (uint64_t)r->B;
+        } else {
+            r->state = kFailed;
+        }
+        r->t_done = now;
+        k += r->B;
+        stats.completed++;
+        stats.in_flight--;
+    }
+    arena.release(s.arena_off);
+    stats.arena_bytes_in_use = arena.in_use();
+    s.reqs.clear();
+    s.busy = false;
+    cv_done.notify_all();
+    return true;
+}
+
+bool rgb_server::launch(Slot& s) {
+    int64_t B = 0, N = 0;
+    uint64_t off = UINT64_MAX;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        const int64_t cap = opts.max_batch_lps;
+        const uint64_t room = arena.largest_free();
+        while (!queue.empty()) {
+            Request* r = queue.front();
+            if (opts.one_request_per_batch && !s.reqs.empty()) break;
+            if (B + r->B > cap) break;
+            if (arena.rounded(Layout(B + r->B, N + r->N).total) > room) break;
+            queue.pop_front();
+            s.reqs.push_back(r);
+            B += r->B;
+            N += r->N;
+        }
+        if (s.reqs.empty()) return false;
+        off = arena.alloc(Layout(B, N).total);
+        if (off == UINT64_MAX) {  // cannot happen: the block was sized against the largest free one
+            for (auto it = s.reqs.rbegin(); it != s.reqs.rend(); ++it) queue.push_front(*it);
+            s.reqs.clear();
+            return false;
+        }
+        for (Request* r : s.reqs) r->state = kAdmitted;
+        stats.pending = (int32_t)queue.size();
+        stats.in_flight += (int32_t)s.reqs.size();
+        stats.micro_batches++;
+        stats.arena_bytes_in_use = arena.in_use();
+        stats.arena_bytes_peak = std::max(stats.arena_bytes_peak, (uint64_t)arena.in_use());
+    }
+    Layout L(B, N);
+    bool ok = true;
+    if (s.pinned_cap < L.total) {
+        if (s.pinned) (void)hipHostFree(s.pinned);
+        s.pinned = nullptr;
+        s.pinned_cap = 0;
+        size_t want = std::max(L.total, (size_t)1 << 20);
+        if (hipHostMalloc((void**)&s.pinned, want, hipHostMallocDefault) == hipSuccess) s.pinned_cap = want;
+        else ok = false;
+    }
+    if (ok) {
+        // stage: offsets shifted by each request's first row, then the arrays back to back
+        char* p = s.pinned;
+        int64_t* offs = reinterpret_cast<int64_t*>(p + L.offsets);
+        int64_t lp = 0, row = 0;
+        for (Request* r : s.reqs) {
+            for (int64_t k = 0; k < r->B; ++k) offs[lp + k] = row + r->offsets[k];
+            std::memcpy(p + L.cx + 4 * lp, r->cx.data(), 4 * (size_t)r->B);
+            std::memcpy(p + L.cy + 4 * lp, r->cy.data(), 4 * (size_t)r->B);
+            std::memcpy(p + L.ax + 4 * row, r->ax.data(), 4 * (size_t)r->N);
+            std::memcpy(p + L.ay + 4 * row, r->ay.data(), 4 * (size_t)r->N);
+            std::memcpy(p + L.b + 4 * row, r->b.data(), 4 * (size_t)r->N);
+            lp += r->B;
+            row += r->N;
+        }
+        offs[lp] = row;
+        char* d = arena_mem + off;
+        ok = hipMemcpyAsync(d, p, L.in_bytes, hipMemcpyHostToDevice, s.stream) == hipSuccess;
+        if (ok) {
+            rgb_solve_opts_t so{};
+            so.variant = opts.variant;
+            ok = rgb_solve_batch(ctx, B, N, reinterpret_cast<const int64_t*>(d + L.offsets),
+                                 reinterpret_cast<const float*>(d + L.ax), reinterpret_cast<const float*>(d + L.ay),
+                                 reinterpret_cast<const float*>(d + L.b), reinterpret_cast<const float*>(d + L.cx),
+                                 reinterpret_cast<const float*>(d + L.cy), reinterpret_cast<float*>(d + L.x),
+                                 reinterpret_cast<float*>(d + L.y), reinterpret_cast<int32_t*>(d + L.st), &so,
+                                 s.stream) == RGB_OK;
+        }
+        if (ok) ok = hipMemcpyAsync(p + L.x, d + L.x, L.total - L.x, hipMemcpyDeviceToHost, s.stream) == hipSuccess;
+        if (ok) ok = hipEventRecord(s.done, s.stream) == hipSuccess;
+    }
+    s.arena_off = off;
+    s.B = B;
+    s.N = N;
+    s.busy = true;
+    if (!ok) {
+        (void)hipStreamSynchronize(s.stream);
+        std::lock_guard<std::mutex> lk(mu);
+        for (Request* r : s.reqs) {
+            r->state = kFailed;
+            r->t_done = Clock::now();
+            stats.completed++;
+            stats.in_flight--;
+        }
+        arena.release(off);
+        s.reqs.clear();
+        s.busy = false;
+        cv_done.notify_all();
+    }
+    return true;
+}
+
+void rgb_server::run() {
+    (void)hipSetDevice(device);
+    while (true) {
+        bool progressed = false;
+        bool any_busy = false;
+        for (auto& s : slots)
+            if (s.busy) progressed |= retire(s);
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            if (stop) break;
+        }
+        for (auto& s : slots)
+            if (!s.busy) progressed |= launch(s);
+        for (auto& s : slots) any_busy |= s.busy;
+        if (progressed) continue;
+        std::unique_lock<std::mutex> lk(mu);
+        if (stop) break;
+        if (any_busy) cv_work.wait_for(lk, std::chrono::microseconds(20));
+        else cv_work.wait_for(lk, std::chrono::milliseconds(50), [&] { return stop || !queue.empty(); });
+    }
+    // drain: wait for the admitted micro-batches, then retire them
+    for (auto& s : slots)
+        if (s.busy) {
+            (void)hipStreamSynchronize(s.stream);
+            retire(s);
+        }
+}
+
+extern "C" {
+
+rgb_err_t rgb_server_create(rgb_ctx_t* ctx, const rgb_server_opts_t* opts, rgb_server_t** out) {
+    if (!ctx || !out) return RGB_ERR_INVALID_ARG;
+    *out = nullptr;
+    rgb_server_opts_t o{};
+    if (opts) o = *opts;
+    if (o.hbm_budget == 0) o.hbm_budget = (uint64_t)1 << 30;
+    if (o.n_streams == 0) o.n_streams = 4;
+    if (o.max_batch_lps == 0) o.max_batch_lps = 65536;
+    if (o.max_pending == 0) o.max_pending = 65536;
+    if (o.n_streams < 1 || o.n_streams > 16 || o.max_batch_lps < 1 || o.max_pending < 1 ||
+        o.variant < RGB_VARIANT_AUTO || o.variant > RGB_VARIANT_BINNED || o.hbm_budget < 4096)
+        return RGB_ERR_INVALID_ARG;
+    int prev = 0;
+    if (hipGetDevice(&prev) != hipSuccess) return RGB_ERR_DEVICE;
+    const int dev = rgb::ctx_device(ctx);
+    if (dev != prev && hipSetDevice(dev) != hipSuccess) return RGB_ERR_DEVICE;
+    struct Restore {
+        int d;
+        ~Restore() { (void)hipSetDevice(d); }
+    } restore{prev};
+    rgb_server_t* s = new (std::nothrow) rgb_server_t();
+    if (!s) return RGB_ERR_OOM;
+    s->opts = o;
+    s->device = dev;
+    // the server's own context on ctx's device, with ctx's tuning
+    rgb_tuning_t t;
+    if (rgb_ctx_get_tuning(ctx, &t) != RGB_OK || rgb_ctx_create(dev, &s->ctx) != RGB_OK ||
+        rgb_ctx_set_tuning(s->ctx, &t) != RGB_OK) {
+        rgb_server_destroy(s);
+        return RGB_ERR_DEVICE;
+    }
+    if (hipMalloc((void**)&s->arena_mem, o.hbm_budget) != hipSuccess) {
+        rgb_server_destroy(s);
+        return RGB_ERR_OOM;
+    }
+    s->arena = rgb::Arena(o.hbm_budget, 256);
+    s->slots.resize((size_t)o.n_streams);
+    for (auto& sl : s->slots) {
+        if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess) {
+            rgb_server_destroy(s);
+            return RGB_ERR_DEVICE;
+        }
+    }
+    s->thr = std::thread([s] { s->run(); });
+    *out = s;
+    return RGB_OK;
+}
+
+rgb_err_t rgb_server_submit(rgb_server_t* srv, int64_t num_lps, int64_t num_constraints, const int64_t* offsets,
+                            const float* ax, const float* ay, const float* b, const float* cx, const float* cy,
+                            uint64_t* ticket) {
+    if (!srv || !ticket || num_lps < 0 || num_constraints < 0 || !offsets) return RGB_ERR_INVALID_ARG;
+    if (num_lps > 0 && (!cx || !cy)) return RGB_ERR_INVALID_ARG;
+    if (num_constraints > 0 && (!ax || !ay || !b)) return RGB_ERR_INVALID_ARG;
+    auto t0 = Clock::now();
+    if (num_lps > srv->opts.max_batch_lps ||
+        srv->arena.rounded(Layout(num_lps, num_constraints).total) > srv->arena.capacity()) {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        srv->stats.rejected_too_large++;
+        return RGB_ERR_TOO_LARGE;
+    }
+    // offsets must tile [0, num_constraints): a request reads only its own rows
+    // even after it is packed into a micro-batch with others
+    if (offsets[0] != 0 || offsets[num_lps] != num_constraints) return RGB_ERR_INVALID_ARG;
+    for (int64_t k = 0; k < num_lps; ++k)
+        if (offsets[k + 1] < offsets[k]) return RGB_ERR_INVALID_ARG;
+    auto r = std::make_unique<Request>();
+    r->B = num_lps;
+    r->N = num_constraints;
+    r->offsets.assign(offsets, offsets + num_lps + 1);
+    r->ax.assign(ax, ax + num_constraints);
+    r->ay.assign(ay, ay + num_constraints);
+    r->b.assign(b, b + num_constraints);
+    r->cx.assign(cx, cx + num_lps);
+    r->cy.assign(cy, cy + num_lps);
+    r->x.resize((size_t)num_lps);
+    r->y.resize((size_t)num_lps);
+    r->st.resize((size_t)num_lps);
+    r->t_submit = t0;
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        if ((int64_t)srv->queue.size() >= srv->opts.max_pending) {
+            srv->stats.rejected_busy++;
+            return RGB_ERR_BUSY;
+        }
+        r->id = srv->next_id++;
+        *ticket = r->id;
+        srv->queue.push_back(r.get());
+        srv->reqs[r->id] = std::move(r);
+        srv->stats.submitted++;
+        srv->stats.pending = (int32_t)srv->queue.size();
+    }
+    srv->cv_work.notify_one();
+    return RGB_OK;
+}
+
+rgb_err_t rgb_server_poll(rgb_server_t* srv, uint64_t ticket, int32_t wait_ms, float* x_out, float* y_out,
+                          int32_t* status_out, double* latency_ms, int32_t* done) {
+    if (!srv || !done) return RGB_ERR_INVALID_ARG;
+    *done = 0;
+    std::unique_lock<std::mutex> lk(srv->mu);
+    auto it = srv->reqs.find(ticket);
+    if (it == srv->reqs.end()) return RGB_ERR_NOT_FOUND;
+    Request* r = it->second.get();
+    auto finished = [&] { return r->state == kDone || r->state == kFailed; };
+    if (!finished() && wait_ms != 0) {
+        if (wait_ms < 0) srv->cv_done.wait(lk, finished);
+        else srv->cv_done.wait_for(lk, std::chrono::milliseconds(wait_ms), finished);
+    }
+    if (!finished()) return RGB_OK;
+    if (r->B > 0 && (!x_out || !y_out || !status_out)) return RGB_ERR_INVALID_ARG;
+    rgb_err_t rc = RGB_OK;
+    if (r->state == kDone) {
+        std::memcpy(x_out, r->x.data(), 4 * (size_t)r->B);
+        std::memcpy(y_out, r->y.data(), 4 * (size_t)r->B);
+        std::memcpy(status_out, r->st.data(), 4 * (size_t)r->B);
+    } else {
+        rc = RGB_ERR_DEVICE;
+    }
+    if (latency_ms) *latency_ms = std::chrono::duration<double, std::milli>(r->t_done - r->t_submit).count();
+    *done = 1;
+    srv->reqs.erase(it);
+    return rc;
+}
+
+rgb_err_t rgb_server_stats(rgb_server_t* srv, rgb_server_stats_t* out) {
+    if (!srv || !out) return RGB_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(srv->mu);
+    *out = srv->stats;
+    return RGB_OK;
+}
+
+rgb_err_t rgb_server_destroy(rgb_server_t* srv) {
+    if (!srv) return RGB_OK;
+    if (srv->thr.joinable()) {
+        {
+            std::lock_guard<std::mutex> lk(srv->mu);
+            srv->stop = true;
+        }
+        srv->cv_work.notify_all();
+        srv->thr.join();
+    }
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        for (Request* r : srv->queue) {
+            r->state = kFailed;
+            r->t_done = Clock::now();
+        }
+        srv->queue.clear();
+    }
+    srv->cv_done.notify_all();
+    for (auto& sl : srv->slots) {
+        if (sl.stream) (void)hipStreamSynchronize(sl.stream);
+        if (sl.done) (void)hipEventDestroy(sl.done);
+        if (sl.stream) (void)hipStreamDestroy(sl.stream);
+        if (sl.pinned) (void)hipHostFree(sl.pinned);
+    }
+    if (srv->arena_mem) (void)hipFree(srv->arena_mem);
+    if (srv->ctx) rgb_ctx_destroy(srv->ctx);
+    delete srv;
+    return RGB_OK;
+}
+
+}  // extern "C"

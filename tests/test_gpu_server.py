@@ -1,0 +1,114 @@
+"""GPU: the continuous-batching server (rgb_server_*).
+
+Each request's result must be the same whether it is solved alone or packed
+into micro-batches with other requests that arrive while earlier ones are
+on the GPU; budget rejection and backpressure must work; and every result
+matches the FP64 oracle."""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import lpcheck
+from paper_1902_04995_amd import gen
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def rgb():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_1902_04995_amd as rgb
+    rgb.lib()
+    return rgb
+
+
+def _requests(n, seed):
+    rng = gen.rng_for(99, seed)
+    out = []
+    for _ in range(n):
+        r = gen.served_request(rng, max_lps=600, m_lo=16, m_hi=700)
+        out.append(r)
+    return out
+
+
+def test_alone_vs_mix(rgb, oracle_lib):
+    import torch
+    reqs = _requests(40, seed=1)
+    # alone: each request as its own device solve
+    alone = []
+    for r in reqs:
+        x, y, st = rgb.DeviceBatch(r, "cuda:0").solve(variant="plain")
+        torch.cuda.synchronize()
+        alone.append((x.cpu().numpy(), y.cpu().numpy(), st.cpu().numpy()))
+    srv = rgb.Server(n_streams=3, max_batch_lps=1500, hbm_budget=64 << 20)
+    _say("[gpu] server burst of 40 requests")
+    tickets = []
+    for i, r in enumerate(reqs):
+        tickets.append(srv.submit(r))
+        if i % 7 == 3:
+            time.sleep(0.002)  # some arrive while others run
+    res = [srv.wait(t) for t in tickets]
+    stats = srv.stats()
+    _say(f"[gpu] server stats {stats}")
+    assert stats["completed"] == 40 and stats["micro_batches"] < 40  # requests were batched together
+    for r, (x, y, st, lat), (ax_, ay_, as_) in zip(reqs, res, alone):
+        assert lat >= 0
+        assert np.array_equal(st, as_)
+        assert np.array_equal(x, ax_, equal_nan=True) and np.array_equal(y, ay_, equal_nan=True)
+        ref = oracle_lib.solve(r)
+        bs, bx = lpcheck.compare(st, x, y, ref["status"], ref["x"], ref["y"])
+        assert len(bs) == 0 and len(bx) == 0
+    srv.close()
+
+
+def test_budget_and_backpressure(rgb):
+    srv = rgb.Server(n_streams=1, max_batch_lps=300, hbm_budget=1 << 20, max_pending=4)
+    big = gen.uniform_batch(500, 64, seed=3)
+    with pytest.raises(rgb.RequestTooLarge):
+        srv.submit(big)  # more LPs than a micro-batch may hold
+    wide = gen.uniform_batch(200, 600, seed=3)
+    with pytest.raises(rgb.RequestTooLarge):
+        srv.submit(wide)  # more bytes than the arena
+    small = gen.uniform_batch(250, 256, seed=4)
+    tickets, busy = [], 0
+    for _ in range(40):
+        try:
+            tickets.append(srv.submit(small))
+        except rgb.ServerBusy:
+            busy += 1
+    _say(f"[gpu] accepted {len(tickets)}, busy {busy}")
+    assert busy > 0 and len(tickets) >= 4
+    first = None
+    for t in tickets:
+        x, y, st, lat = srv.wait(t)
+        if first is None:
+            first = (x, y, st)
+        assert np.array_equal(st, first[2]) and np.array_equal(x, first[0], equal_nan=True)
+    st = srv.stats()
+    assert st["rejected_too_large"] == 2 and st["rejected_busy"] == busy and st["arena_bytes_in_use"] == 0
+    with pytest.raises(rgb.RgbError):
+        srv.poll(12345678)
+    srv.close()
+
+
+def test_empty_and_invalid_requests(rgb):
+    srv = rgb.Server(n_streams=2)
+    empty = gen.Batch(np.zeros(1, np.int64), np.zeros(0, np.float32), np.zeros(0, np.float32),
+                      np.zeros(0, np.float32), np.zeros(0, np.float32), np.zeros(0, np.float32), np.zeros(0, np.int8))
+    t = srv.submit(empty)
+    x, y, st, _ = srv.wait(t)
+    assert x.size == 0
+    bad = gen.uniform_batch(4, 8, seed=5)
+    bad.offsets = bad.offsets.copy()
+    bad.offsets[2] = bad.offsets[1] - 1  # decreasing
+    with pytest.raises(rgb.RgbError):
+        srv.submit(bad)
+    srv.close()

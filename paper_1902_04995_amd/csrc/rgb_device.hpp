@@ -154,13 +154,27 @@ __device__ __forceinline__ bool parallel_empties(float ax, float ay, float b, co
 
 // One work unit (Sec. 3): fold row (ax, ay, b) into the bounds on line L.
 // hi = min over right bounds (u_right), lo = max over left bounds (u_left).
-__device__ __forceinline__ void work_unit(float ax, float ay, float b, const Line& L, float& hi, float& lo,
-                                          bool& par_inf) {
+// Rows with D >= 0 count as right bounds, so a parallel row (D = 0) gives
+// sigma = r * (1/0) = +-inf: harmless when +inf (or NaN for r = 0), and -inf
+// when it may empty the line.  hi = -inf therefore flags "look again": the
+// caller reruns the rows with exact_pass(), which decides parallel rows in
+// FP64.  Ties and NaN positions leave a bound unchanged.
+__device__ __forceinline__ void work_unit(float ax, float ay, float b, const Line& L, float& hi, float& lo) {
     float D;
     float sig = wu_sigma(ax, ay, b, L, D);
-    hi = __builtin_fminf(hi, D > 0.0f ? sig : __builtin_huge_valf());
-    lo = __builtin_fmaxf(lo, D < 0.0f ? sig : -__builtin_huge_valf());
-    if (__builtin_expect(D == 0.0f, 0)) par_inf |= parallel_empties(ax, ay, b, L);
+    hi = (D >= 0.0f && sig < hi) ? sig : hi;
+    lo = (D < 0.0f && sig > lo) ? sig : lo;
+}
+
+// The careful version of work_unit for the rare rerun: parallel rows are
+// left out of the bounds and decided exactly.
+__device__ __forceinline__ void work_unit_exact(float ax, float ay, float b, const Line& L, float& hi, float& lo,
+                                                bool& par_inf) {
+    float D;
+    float sig = wu_sigma(ax, ay, b, L, D);
+    if (D > 0.0f) hi = sig < hi ? sig : hi;
+    else if (D < 0.0f) lo = sig > lo ? sig : lo;
+    else par_inf |= parallel_empties(ax, ay, b, L);
 }
 
 // Exact-in-FP64 re-decision of u_left > u_right from the two bounding rows.

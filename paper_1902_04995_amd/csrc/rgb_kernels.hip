@@ -16,6 +16,8 @@
 // kernel returns bit-identical results.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "rgb_device.hpp"
 #include "rgb_internal.hpp"
 
@@ -69,8 +71,13 @@ __global__ __launch_bounds__(256) void k_plain(Problem P) {
         Line L;
         make_line(L, ax, ay, b);
         float hi = __builtin_huge_valf(), lo = -__builtin_huge_valf();
+        for (int h = 0; h < i; ++h) work_unit(rax[h], ray[h], rb[h], L, hi, lo);
         bool par = false;
-        for (int h = 0; h < i; ++h) work_unit(rax[h], ray[h], rb[h], L, hi, lo, par);
+        if (hi == -__builtin_huge_valf()) {  // rare: a row parallel to line i, or an overflow
+            hi = __builtin_huge_valf();
+            lo = -__builtin_huge_valf();
+            for (int h = 0; h < i; ++h) work_unit_exact(rax[h], ray[h], rb[h], L, hi, lo, par);
+        }
         if (par) {
             set_dead(st, kInfeasible);
             break;
@@ -132,8 +139,9 @@ __device__ __forceinline__ float dpp_f(float v) {
         return v;                                                                    \
     }
 
-__device__ __forceinline__ float fmin_(float a, float b) { return __builtin_fminf(a, b); }
-__device__ __forceinline__ float fmax_(float a, float b) { return __builtin_fmaxf(a, b); }
+// bounds are never NaN, so a compare and select is an exact min/max
+__device__ __forceinline__ float fmin_(float a, float b) { return b < a ? b : a; }
+__device__ __forceinline__ float fmax_(float a, float b) { return b > a ? b : a; }
 __device__ __forceinline__ int imin_(int a, int b) { return a < b ? a : b; }
 RGB_GROUP_REDUCE(group_min, float, fmin_, dpp_f)
 RGB_GROUP_REDUCE(group_max, float, fmax_, dpp_f)
@@ -144,14 +152,39 @@ __device__ __forceinline__ uint64_t group_mask(int lg, int gbase) {
     return lg >= 6 ? ~0ull : (((1ull << (1 << lg)) - 1ull) << gbase);
 }
 
+// Rows of one LP, addressed from the batch's (wave-uniform) array bases.
+// With WIDE = false the LP's first row is a 32-bit byte offset, so loads use
+// the scalar-base + 32-bit vector-offset form and one add per step; batches
+// of 2^30 rows or more use 64-bit indices (WIDE = true).
+template <bool WIDE>
+struct RowRef {
+    const float* ax;
+    const float* ay;
+    const float* b;
+    typename std::conditional<WIDE, int64_t, uint32_t>::type first;
+
+    __device__ __forceinline__ float ld(const float* base, int h) const {
+        if constexpr (WIDE) {
+            return base[first + h];
+        } else {
+            uint32_t off = (first + (uint32_t)h) * 4u;
+            return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(base) + off);
+        }
+    }
+    __device__ __forceinline__ float x(int h) const { return ld(ax, h); }
+    __device__ __forceinline__ float y(int h) const { return ld(ay, h); }
+    __device__ __forceinline__ float c(int h) const { return ld(b, h); }
+};
+
 // Smallest row h < v of the LP whose bound on line L equals `target` on the
 // given side; all lanes of the group must be active.
-__device__ __forceinline__ int group_find(const float* rax, const float* ray, const float* rb, int v, const Line& L,
-                                          float target, bool up, int gl, int lg) {
+template <bool WIDE>
+__device__ __forceinline__ int group_find(const RowRef<WIDE>& R, int v, const Line& L, float target, bool up, int gl,
+                                          int lg) {
     int best = kNoIdx;
     for (int h = gl; h < v; h += (1 << lg)) {
         float D;
-        float s = wu_sigma(rax[h], ray[h], rb[h], L, D);
+        float s = wu_sigma(R.x(h), R.y(h), R.c(h), L, D);
         bool hit = (up ? D > 0.0f : D < 0.0f) && s == target;
         best = (hit && h < best) ? h : best;
     }
@@ -162,7 +195,7 @@ __device__ __forceinline__ int group_find(const float* rax, const float* ray, co
 // the wave calls this together, each group with its own LP.  LGC >= 0 fixes
 // lg at compile time; LGC = -1 takes it from lg_rt (one body for any width,
 // which keeps the persistent kernel's register count at one width's).
-template <int LGC>
+template <int LGC, bool WIDE>
 __device__ __forceinline__ void solve_group(const Problem& P, int64_t lp, int lg_rt = 0) {
     const int lg = LGC >= 0 ? LGC : lg_rt;
     const int G = 1 << lg;
@@ -180,9 +213,7 @@ __device__ __forceinline__ void solve_group(const Problem& P, int64_t lp, int lg
         cy = P.cy[lp];
         ok = lp_range(P, lp, start, m) && __builtin_isfinite(cx) && __builtin_isfinite(cy);
     }
-    const float* rax = P.ax + start;
-    const float* ray = P.ay + start;
-    const float* rb = P.b + start;
+    RowRef<WIDE> R{P.ax, P.ay, P.b, (typename std::conditional<WIDE, int64_t, uint32_t>::type)start};
 
     LpState st;
     init_state(st, cx, cy);
@@ -198,9 +229,9 @@ __device__ __forceinline__ void solve_group(const Problem& P, int64_t lp, int lg
         bool in = !done && idx < m;
         float tx = 0.0f, ty = 0.0f, tb = 0.0f;
         if (in) {
-            tx = rax[idx];
-            ty = ray[idx];
-            tb = rb[idx];
+            tx = R.x(idx);
+            ty = R.y(idx);
+            tb = R.c(idx);
         }
         bool fin = finite3(tx, ty, tb);
         bad |= in && !fin;
@@ -227,10 +258,17 @@ __device__ __forceinline__ void solve_group(const Problem& P, int64_t lp, int lg
                 Line L;
                 make_line(L, lx, ly, lb);
                 float hi = __builtin_huge_valf(), lo = -__builtin_huge_valf();
-                bool par = false;
-                for (int h = gl; h < v; h += G) work_unit(rax[h], ray[h], rb[h], L, hi, lo, par);
+                for (int h = gl; h < v; h += G) work_unit(R.x(h), R.y(h), R.c(h), L, hi, lo);
                 hi = group_min(hi, lg);
                 lo = group_max(lo, lg);
+                bool par = false;
+                if (hi == -__builtin_huge_valf()) {  // rare: a row parallel to line v, or an overflow
+                    hi = __builtin_huge_valf();
+                    lo = -__builtin_huge_valf();
+                    for (int h = gl; h < v; h += G) work_unit_exact(R.x(h), R.y(h), R.c(h), L, hi, lo, par);
+                    hi = group_min(hi, lg);
+                    lo = group_max(lo, lg);
+                }
                 par = (__ballot(par) & gmask) != 0;
                 if (par) {
                     set_dead(st, kInfeasible);
@@ -239,10 +277,10 @@ __device__ __forceinline__ void solve_group(const Problem& P, int64_t lp, int lg
                     if (!__builtin_isinf(hi) && !__builtin_isinf(lo)) {
                         inf = lo > hi;
                         if (near_tie(L, hi, lo)) {
-                            int il = group_find(rax, ray, rb, v, L, lo, false, gl, lg);
-                            int ih = group_find(rax, ray, rb, v, L, hi, true, gl, lg);
+                            int il = group_find(R, v, L, lo, false, gl, lg);
+                            int ih = group_find(R, v, L, hi, true, gl, lg);
                             if (il != kNoIdx && ih != kNoIdx)
-                                inf = exact_lo_gt_hi(L, rax[il], ray[il], rb[il], rax[ih], ray[ih], rb[ih]);
+                                inf = exact_lo_gt_hi(L, R.x(il), R.y(il), R.c(il), R.x(ih), R.y(ih), R.c(ih));
                         }
                     }
                     if (inf) set_dead(st, kInfeasible);
@@ -255,29 +293,29 @@ __device__ __forceinline__ void solve_group(const Problem& P, int64_t lp, int lg
     }
     // an LP that died early still gets its remaining rows checked for non-finite values
     if (lp >= 0 && st.kind == kDead && st.dead_status == kInfeasible)
-        for (int idx = cur + gl; idx < m; idx += G) bad |= !finite3(rax[idx], ray[idx], rb[idx]);
+        for (int idx = cur + gl; idx < m; idx += G) bad |= !finite3(R.x(idx), R.y(idx), R.c(idx));
     if ((__ballot(bad) & gmask) != 0) set_dead(st, kInvalid);
 
     int h = -1;
     if (__ballot(st.kind == kPoint) != 0) {
         if (st.kind == kPoint) {
             Line L;
-            make_line(L, rax[st.l], ray[st.l], rb[st.l]);
-            h = group_find(rax, ray, rb, st.l, L, st.sig, st.up, gl, lg);
+            make_line(L, R.x(st.l), R.y(st.l), R.c(st.l));
+            h = group_find(R, st.l, L, st.sig, st.up, gl, lg);
             if (h == kNoIdx) h = st.l;  // cannot happen (the bound came from these bits); x is NaN then
         }
     }
     if (lp >= 0 && gl == 0) finish_lp(P, lp, start, st, h, n1d);
 }
 
-template <int G>
+template <int G, bool WIDE>
 __global__ __launch_bounds__(256) void k_group(Problem P) {
     constexpr int LPS_PER_BLOCK = 256 / G;
     int64_t q = (int64_t)blockIdx.x * LPS_PER_BLOCK + threadIdx.x / G;
     int64_t lp = -1;
     if (q < P.num_lps) lp = P.order ? (int64_t)P.order[q] : q;
     constexpr int LG = G == 4 ? 2 : G == 8 ? 3 : G == 16 ? 4 : G == 32 ? 5 : 6;
-    solve_group<LG>(P, lp);
+    solve_group<LG, WIDE>(P, lp);
 }
 
 // ---------------------------------------------------------------------------
@@ -387,7 +425,7 @@ __device__ __forceinline__ int sub_batch_slot(const QueueHeader& Q, int k) {
 
 // Solve sub-batch k (class slot j) of the queue: 64/G LPs of one class,
 // G = 2^lg with lg = Q.lg[j] (fixed at compile time when LGC >= 0).
-template <int LGC>
+template <int LGC, bool WIDE>
 __device__ __forceinline__ void run_sub_batch(const Problem& P, const Workspace& W, const QueueHeader& Q, int k,
                                               int j) {
     const int lg = LGC >= 0 ? LGC : Q.lg[j];
@@ -396,7 +434,7 @@ __device__ __forceinline__ void run_sub_batch(const Problem& P, const Workspace&
     int q = first + (__lane_id() >> lg);
     int64_t lp = q < Q.e_end[j] ? (int64_t)W.order[q] : -1;
     if (lp >= P.num_lps) lp = -1;  // never read outside the batch, whatever the queue holds
-    solve_group<LGC>(P, lp, lg);
+    solve_group<LGC, WIDE>(P, lp, lg);
 }
 
 __device__ __forceinline__ void load_header(QueueHeader& Qs, const Workspace& W) {
@@ -412,6 +450,7 @@ __device__ __forceinline__ void load_header(QueueHeader& Qs, const Workspace& W)
 // XCD's waves (workgroups are spread over the XCDs round-robin) mostly hit
 // their own counter.  A wave whose part is drained takes from the others,
 // `chunk` sub-batches per pop.  Every wave exits once all parts are drained.
+template <bool WIDE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_persist(Problem P, Workspace W,
                                                                                          PersistPlan plan) {
     __shared__ QueueHeader Qs;
@@ -419,7 +458,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k
     const QueueHeader& Q = Qs;
     const int waves = (int)(gridDim.x * (blockDim.x >> 6));
     const int wid = (int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
-    for (int k = wid; k < Q.dyn_begin; k += waves) run_sub_batch<-1>(P, W, Q, k, sub_batch_slot(Q, k));
+    for (int k = wid; k < Q.dyn_begin; k += waves) run_sub_batch<-1, WIDE>(P, W, Q, k, sub_batch_slot(Q, k));
     const int chunk = plan.chunk > 0 ? plan.chunk : 1;
     const int ndyn = Q.num_sb - Q.dyn_begin;
     for (int t = 0; t < kQueues; ++t) {
@@ -433,7 +472,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k
             int i1 = min(i0 + chunk, len);
             for (int i = i0; i < i1; ++i) {
                 int k = Q.dyn_begin + x + i * kQueues;
-                run_sub_batch<-1>(P, W, Q, k, sub_batch_slot(Q, k));
+                run_sub_batch<-1, WIDE>(P, W, Q, k, sub_batch_slot(Q, k));
             }
         }
     }
@@ -442,6 +481,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k
 // Binned, non-persistent: one wave per sub-batch in queue order (largest LPs
 // first); the grid is an upper bound and surplus waves exit at once.  The
 // hardware dispatcher starts a new wave wherever one finishes.
+template <bool WIDE>
 __global__ __launch_bounds__(256) void k_binned(Problem P, Workspace W) {
     __shared__ QueueHeader Qs;
     load_header(Qs, W);
@@ -449,17 +489,20 @@ __global__ __launch_bounds__(256) void k_binned(Problem P, Workspace W) {
     if (k >= Qs.num_sb) return;
     int j = sub_batch_slot(Qs, k);
     switch (Qs.lg[j]) {
-        case 2: run_sub_batch<2>(P, W, Qs, k, j); break;
-        case 3: run_sub_batch<3>(P, W, Qs, k, j); break;
-        case 4: run_sub_batch<4>(P, W, Qs, k, j); break;
-        case 5: run_sub_batch<5>(P, W, Qs, k, j); break;
-        default: run_sub_batch<6>(P, W, Qs, k, j); break;
+        case 2: run_sub_batch<2, WIDE>(P, W, Qs, k, j); break;
+        case 3: run_sub_batch<3, WIDE>(P, W, Qs, k, j); break;
+        case 4: run_sub_batch<4, WIDE>(P, W, Qs, k, j); break;
+        case 5: run_sub_batch<5, WIDE>(P, W, Qs, k, j); break;
+        default: run_sub_batch<6, WIDE>(P, W, Qs, k, j); break;
     }
 }
 
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
+// 32-bit byte offsets reach every row of the batch?
+static bool wide_rows(const Problem& P) { return P.num_constraints >= (int64_t(1) << 30); }
+
 hipError_t launch_plain(const Problem& P, hipStream_t stream) {
     if (P.num_lps == 0) return hipSuccess;
     int64_t blocks = (P.num_lps + 255) / 256;
@@ -471,7 +514,8 @@ template <int G>
 static hipError_t launch_group_t(const Problem& P, hipStream_t stream) {
     constexpr int LPS_PER_BLOCK = 256 / G;
     int64_t blocks = (P.num_lps + LPS_PER_BLOCK - 1) / LPS_PER_BLOCK;
-    hipLaunchKernelGGL((k_group<G>), dim3((unsigned)blocks), dim3(256), 0, stream, P);
+    if (wide_rows(P)) hipLaunchKernelGGL((k_group<G, true>), dim3((unsigned)blocks), dim3(256), 0, stream, P);
+    else hipLaunchKernelGGL((k_group<G, false>), dim3((unsigned)blocks), dim3(256), 0, stream, P);
     return hipGetLastError();
 }
 
@@ -486,13 +530,16 @@ hipError_t launch_persistent(const Problem& P, const Workspace& W, const Persist
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(kBinBlocks), 0, stream, W, plan);
     hipLaunchKernelGGL(k_scatter, dim3(kBinBlocks), dim3(256), 0, stream, P, W);
     if (ev_begin) (void)hipEventRecord(ev_begin, stream);
+    const bool wide = wide_rows(P);
     if (binned) {
         // at most one sub-batch per LP plus one partial sub-batch per class
         int64_t max_sb = P.num_lps + kClasses;
         int64_t blocks = (max_sb + 3) / 4;
-        hipLaunchKernelGGL(k_binned, dim3((unsigned)blocks), dim3(256), 0, stream, P, W);
+        if (wide) hipLaunchKernelGGL(k_binned<true>, dim3((unsigned)blocks), dim3(256), 0, stream, P, W);
+        else hipLaunchKernelGGL(k_binned<false>, dim3((unsigned)blocks), dim3(256), 0, stream, P, W);
     } else {
-        hipLaunchKernelGGL(k_persist, dim3(grid), dim3(256), 0, stream, P, W, plan);
+        if (wide) hipLaunchKernelGGL(k_persist<true>, dim3(grid), dim3(256), 0, stream, P, W, plan);
+        else hipLaunchKernelGGL(k_persist<false>, dim3(grid), dim3(256), 0, stream, P, W, plan);
     }
     if (ev_end) (void)hipEventRecord(ev_end, stream);
     return hipGetLastError();
@@ -500,7 +547,7 @@ hipError_t launch_persistent(const Problem& P, const Workspace& W, const Persist
 
 int persist_blocks_per_cu() {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_persist, 256, 0) != hipSuccess) return 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_persist<false>, 256, 0) != hipSuccess) return 1;
     return n > 0 ? n : 1;
 }
 

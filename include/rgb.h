@@ -76,13 +76,17 @@ typedef enum {
  * runs one persistent launch that deals the bulk of the work round-robin and
  * the tail from a device queue, largest LPs first; BINNED bins the same way
  * and launches one wave per sub-batch of the queue, leaving the balancing
- * to the hardware dispatcher.  AUTO = PERSISTENT. */
+ * to the hardware dispatcher.  POOLED gives each LP a small scan group (4, 8
+ * or 16 lanes) and serves the 1D LPs of all LPs of a wave that wait with a
+ * violated row in one round, their work units dealt over the whole wave.
+ * AUTO = the context's tuning (PERSISTENT unless retuned). */
 typedef enum {
     RGB_VARIANT_AUTO = 0,
     RGB_VARIANT_PLAIN = 1,
     RGB_VARIANT_BATCHED = 2,
     RGB_VARIANT_PERSISTENT = 3,
-    RGB_VARIANT_BINNED = 4
+    RGB_VARIANT_BINNED = 4,
+    RGB_VARIANT_POOLED = 5
 } rgb_variant_t;
 
 typedef struct rgb_ctx rgb_ctx_t;
@@ -91,8 +95,10 @@ typedef struct rgb_ctx rgb_ctx_t;
  * for every numeric field. */
 typedef struct {
     int32_t variant;        /* rgb_variant_t */
-    int32_t lanes_per_lp;   /* BATCHED: lanes per LP, one of 4, 8, 16, 32, 64 */
-    int32_t slots;          /* reserved, must be 0 */
+    int32_t lanes_per_lp;   /* BATCHED: lanes per LP, one of 4, 8, 16, 32, 64; POOLED: 4, 8 or 16 */
+    int32_t pool_wait;      /* POOLED: a wave keeps scanning until this many eighths (1..8) of its
+                               live LPs wait with a violated row; -1 = serve every violation at once */
+    int32_t pool_rows;      /* POOLED: rows each lane tests per scan step (1, 2 or 4) */
     int32_t chunk;          /* PERSISTENT: sub-batches taken per queue pop */
     int32_t grid;           /* PERSISTENT: workgroups launched */
     int32_t queue_share;    /* PERSISTENT: share of the sub-batches handed out by the device queue,
@@ -105,7 +111,7 @@ typedef struct {
 /* A launch configuration: kernel family and shape.  rgb_autotune() fills one
  * by measurement; AUTO solves use the context's current one. */
 typedef struct {
-    int32_t variant;        /* RGB_VARIANT_PERSISTENT, RGB_VARIANT_BINNED or RGB_VARIANT_BATCHED */
+    int32_t variant;        /* RGB_VARIANT_PERSISTENT, _BINNED, _BATCHED or _POOLED */
     int32_t log2_lanes[16]; /* PERSISTENT/BINNED: lanes per LP = 2^v (v in 2..6) for size class c,
                                which holds LPs with 2^(c-1) < m <= 2^c rows (class 0: m <= 1,
                                class 15: m > 2^14) */
@@ -113,6 +119,9 @@ typedef struct {
     int32_t queue_share;    /* PERSISTENT: sub-batches handed out by the device queue, in 1/1024 */
     int32_t chunk;          /* PERSISTENT: sub-batches per queue pop (>= 1) */
     int32_t grid;           /* PERSISTENT: workgroups, 0 = all that fit on the device at once */
+    int32_t pool_lanes;     /* POOLED: scan lanes per LP (4, 8 or 16) */
+    int32_t pool_wait;      /* POOLED: wait threshold in eighths, 0 = serve every violation at once */
+    int32_t pool_rows;      /* POOLED: rows each lane tests per scan step (1, 2 or 4) */
     float ms;               /* rgb_autotune: measured time of one solve with this configuration */
 } rgb_tuning_t;
 

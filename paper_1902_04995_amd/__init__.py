@@ -18,7 +18,7 @@ import os
 import threading
 
 OPTIMAL, INFEASIBLE, UNBOUNDED, INVALID = 0, 1, 2, 3
-VARIANTS = {"auto": 0, "plain": 1, "batched": 2, "persistent": 3, "binned": 4}
+VARIANTS = {"auto": 0, "plain": 1, "batched": 2, "persistent": 3, "binned": 4, "pooled": 5}
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librgb.so")
@@ -32,7 +32,8 @@ class RgbError(RuntimeError):
 
 
 class _SolveOpts(ctypes.Structure):
-    _fields_ = [("variant", ctypes.c_int32), ("lanes_per_lp", ctypes.c_int32), ("slots", ctypes.c_int32),
+    _fields_ = [("variant", ctypes.c_int32), ("lanes_per_lp", ctypes.c_int32), ("pool_wait", ctypes.c_int32),
+                ("pool_rows", ctypes.c_int32),
                 ("chunk", ctypes.c_int32), ("grid", ctypes.c_int32), ("queue_share", ctypes.c_int32),
                 ("n_1dlp_out", ctypes.c_void_p), ("ev_begin", ctypes.c_void_p), ("ev_end", ctypes.c_void_p)]
 
@@ -41,12 +42,15 @@ class Tuning(ctypes.Structure):
     """rgb_tuning_t: a launch configuration (see include/rgb.h)."""
     _fields_ = [("variant", ctypes.c_int32), ("log2_lanes", ctypes.c_int32 * 16), ("batched_lanes", ctypes.c_int32),
                 ("queue_share", ctypes.c_int32), ("chunk", ctypes.c_int32), ("grid", ctypes.c_int32),
+                ("pool_lanes", ctypes.c_int32), ("pool_wait", ctypes.c_int32), ("pool_rows", ctypes.c_int32),
                 ("ms", ctypes.c_float)]
 
     def to_dict(self):
         return {"variant": {v: k for k, v in VARIANTS.items()}.get(self.variant, self.variant),
                 "log2_lanes": list(self.log2_lanes), "batched_lanes": self.batched_lanes,
-                "queue_share": self.queue_share, "chunk": self.chunk, "grid": self.grid, "ms": self.ms}
+                "queue_share": self.queue_share, "chunk": self.chunk, "grid": self.grid,
+                "pool_lanes": self.pool_lanes, "pool_wait": self.pool_wait, "pool_rows": self.pool_rows,
+                "ms": self.ms}
 
     @classmethod
     def from_dict(cls, d):
@@ -59,6 +63,9 @@ class Tuning(ctypes.Structure):
         t.queue_share = int(d["queue_share"])
         t.chunk = int(d["chunk"])
         t.grid = int(d.get("grid", 0))
+        t.pool_lanes = int(d.get("pool_lanes", 4))
+        t.pool_wait = int(d.get("pool_wait", 2))
+        t.pool_rows = int(d.get("pool_rows", 4))
         t.ms = float(d.get("ms", 0.0))
         return t
 
@@ -189,12 +196,13 @@ def _check_tensor(t, name, dtype, device):
         raise ValueError(f"{name} must be contiguous")
 
 
-def make_opts(variant="auto", lanes_per_lp=0, slots=0, chunk=0, grid=0, n_1dlp=None, events=None,
-              queue_share=0) -> _SolveOpts:
+def make_opts(variant="auto", lanes_per_lp=0, pool_wait=0, chunk=0, grid=0, n_1dlp=None, events=None,
+              queue_share=0, pool_rows=0) -> _SolveOpts:
     o = _SolveOpts()
     o.variant = VARIANTS[variant] if isinstance(variant, str) else int(variant)
     o.lanes_per_lp = int(lanes_per_lp)
-    o.slots = int(slots)
+    o.pool_wait = int(pool_wait)
+    o.pool_rows = int(pool_rows)
     o.chunk = int(chunk)
     o.grid = int(grid)
     o.queue_share = int(queue_share)
@@ -211,8 +219,8 @@ def _event_handle(ev):
     return ev.cuda_event
 
 
-def solve_batch(offsets, ax, ay, b, cx, cy, *, variant="auto", lanes_per_lp=0, slots=0, chunk=0, grid=0,
-                queue_share=0, want_n_1dlp=False, out=None, stream=None, ctx: Context | None = None, events=None):
+def solve_batch(offsets, ax, ay, b, cx, cy, *, variant="auto", lanes_per_lp=0, pool_wait=0, chunk=0, grid=0,
+                queue_share=0, pool_rows=0, want_n_1dlp=False, out=None, stream=None, ctx: Context | None = None, events=None):
     """Solve a CSR-offset SoA batch held in CUDA tensors (offsets int64[B+1];
     ax, ay, b float32[N]; cx, cy float32[B]).  Enqueues on ``stream`` (default:
     torch's current stream) and returns (x, y, status[, n_1dlp]) tensors that
@@ -239,7 +247,7 @@ def solve_batch(offsets, ax, ay, b, cx, cy, *, variant="auto", lanes_per_lp=0, s
     ctx = ctx or context(dev.index or 0)
     if stream is None:
         stream = torch.cuda.current_stream(dev)
-    opts = make_opts(variant, lanes_per_lp, slots, chunk, grid, n1d, events, queue_share)
+    opts = make_opts(variant, lanes_per_lp, pool_wait, chunk, grid, n1d, events, queue_share, pool_rows)
     rc = lib().rgb_solve_batch(ctx.handle, B, N, _ptr(offsets), _ptr(ax), _ptr(ay), _ptr(b), _ptr(cx), _ptr(cy),
                                _ptr(x), _ptr(y), _ptr(st), ctypes.byref(opts), ctypes.c_void_p(stream.cuda_stream))
     ctx.check(rc, "rgb_solve_batch")
@@ -287,14 +295,15 @@ class Plan:
     """A solve captured as a HIP graph (rgb_plan_create) over fixed buffers."""
 
     def __init__(self, offsets, ax, ay, b, cx, cy, *, variant="auto", lanes_per_lp=0, chunk=0, grid=0,
-                 queue_share=0, out=None, want_n_1dlp=False, ctx: Context | None = None):
+                 queue_share=0, pool_wait=0, pool_rows=0, out=None, want_n_1dlp=False,
+                 ctx: Context | None = None):
         import torch
         dev, B, N, args, out = _batch_args(offsets, ax, ay, b, cx, cy, out)
         self.ctx = ctx or context(dev.index or 0)
         self.out = out
         self.n_1dlp = torch.empty(B, dtype=torch.int32, device=dev) if want_n_1dlp else None
         self._keep = (offsets, ax, ay, b, cx, cy)
-        opts = make_opts(variant, lanes_per_lp, 0, chunk, grid, self.n_1dlp, None, queue_share)
+        opts = make_opts(variant, lanes_per_lp, pool_wait, chunk, grid, self.n_1dlp, None, queue_share, pool_rows)
         h = ctypes.c_void_p()
         rc = lib().rgb_plan_create(self.ctx.handle, B, N, *args, ctypes.byref(opts), ctypes.byref(h))
         self.ctx.check(rc, "rgb_plan_create")

@@ -90,15 +90,19 @@ void default_tuning(rgb_tuning_t& t) {
     t.queue_share = 128;
     t.chunk = 1;
     t.grid = 0;
+    t.pool_lanes = 4;
+    t.pool_wait = 2;
+    t.pool_rows = 4;
 }
 
 bool tuning_valid(const rgb_tuning_t& t) {
-    if (t.variant != RGB_VARIANT_PERSISTENT && t.variant != RGB_VARIANT_BINNED && t.variant != RGB_VARIANT_BATCHED)
+    if (t.variant != RGB_VARIANT_PERSISTENT && t.variant != RGB_VARIANT_BINNED && t.variant != RGB_VARIANT_BATCHED &&
+        t.variant != RGB_VARIANT_POOLED)
         return false;
     for (int c = 0; c < rgb::kClasses; ++c)
         if (t.log2_lanes[c] < 2 || t.log2_lanes[c] > 6) return false;
     return lanes_ok(t.batched_lanes) && t.queue_share >= 0 && t.queue_share <= 1024 && t.chunk >= 1 &&
-           t.grid >= 0;
+           t.grid >= 0 && rgb::pool_supported(t.pool_lanes, t.pool_rows) && t.pool_wait >= 0 && t.pool_wait <= 8;
 }
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
@@ -203,16 +207,24 @@ rgb::Problem make_problem(const Batch& B, int32_t* n1d) {
 rgb_err_t resolve(rgb_ctx_t* ctx, const rgb_solve_opts_t& o, int& variant, rgb_tuning_t& cfg) {
     cfg = ctx->tuning;
     variant = o.variant;
-    if (variant < RGB_VARIANT_AUTO || variant > RGB_VARIANT_BINNED)
+    if (variant < RGB_VARIANT_AUTO || variant > RGB_VARIANT_POOLED)
         return fail(ctx, RGB_ERR_INVALID_ARG, "unknown variant %d", variant);
-    if (o.slots != 0) return fail(ctx, RGB_ERR_INVALID_ARG, "opts.slots is reserved and must be 0");
     if (variant == RGB_VARIANT_AUTO) variant = cfg.variant;
     if (o.lanes_per_lp) {
         if (!lanes_ok(o.lanes_per_lp))
             return fail(ctx, RGB_ERR_INVALID_ARG, "lanes_per_lp=%d is not one of 4, 8, 16, 32, 64", o.lanes_per_lp);
+        if (variant == RGB_VARIANT_POOLED && !rgb::pool_supported(o.lanes_per_lp, 1))
+            return fail(ctx, RGB_ERR_INVALID_ARG, "POOLED takes 4, 8 or 16 lanes per LP, not %d", o.lanes_per_lp);
         cfg.batched_lanes = o.lanes_per_lp;
         for (int c = 0; c < rgb::kClasses; ++c) cfg.log2_lanes[c] = __builtin_ctz(o.lanes_per_lp);
+        if (rgb::pool_supported(o.lanes_per_lp, 1)) cfg.pool_lanes = o.lanes_per_lp;
     }
+    if (o.pool_wait < -1 || o.pool_wait > 8)
+        return fail(ctx, RGB_ERR_INVALID_ARG, "pool_wait %d outside [-1, 8]", o.pool_wait);
+    if (o.pool_wait) cfg.pool_wait = o.pool_wait < 0 ? 0 : o.pool_wait;
+    if (o.pool_rows && !rgb::pool_supported(4, o.pool_rows))
+        return fail(ctx, RGB_ERR_INVALID_ARG, "pool_rows %d is not one of 1, 2, 4", o.pool_rows);
+    if (o.pool_rows) cfg.pool_rows = o.pool_rows;
     if (o.chunk < 0 || o.grid < 0) return fail(ctx, RGB_ERR_INVALID_ARG, "negative chunk or grid");
     if (o.chunk) cfg.chunk = o.chunk;
     if (o.grid) cfg.grid = o.grid;
@@ -233,6 +245,10 @@ rgb_err_t enqueue(rgb_ctx_t* ctx, const rgb::Problem& P, int variant, const rgb_
     } else if (variant == RGB_VARIANT_BATCHED) {
         if (ev0) (void)hipEventRecord(ev0, st);
         e = rgb::launch_group(P, cfg.batched_lanes, st);
+        if (ev1) (void)hipEventRecord(ev1, st);
+    } else if (variant == RGB_VARIANT_POOLED) {
+        if (ev0) (void)hipEventRecord(ev0, st);
+        e = rgb::launch_pool(P, cfg.pool_lanes, cfg.pool_rows, cfg.pool_wait, st);
         if (ev1) (void)hipEventRecord(ev1, st);
     } else {
         rgb::PersistPlan plan{};
@@ -400,6 +416,16 @@ rgb_err_t rgb_autotune(rgb_ctx_t* ctx, int64_t num_lps, int64_t num_constraints,
             c.batched_lanes = g;
             if ((r = try_cfg(c)) != RGB_OK) return r;
         }
+        // POOLED: scan width, rows per lane and wait threshold
+        static const int kPool[][3] = {{4, 4, 2}, {4, 4, 0}, {4, 2, 2}, {8, 4, 2}, {8, 2, 2}, {8, 2, 0}, {16, 2, 2}};
+        for (const auto& pc : kPool) {
+            rgb_tuning_t c = cur;
+            c.variant = RGB_VARIANT_POOLED;
+            c.pool_lanes = pc[0];
+            c.pool_rows = pc[1];
+            c.pool_wait = pc[2];
+            if ((r = try_cfg(c)) != RGB_OK) return r;
+        }
         // 2. rows per size class, from a binning pass
         std::vector<uint8_t> cls((size_t)num_lps);
         std::vector<int64_t> offs((size_t)num_lps + 1);
@@ -425,7 +451,7 @@ rgb_err_t rgb_autotune(rgb_ctx_t* ctx, int64_t num_lps, int64_t num_constraints,
             if (total > 0 && rows[c] * 25 >= total) order.push_back(c);
         std::sort(order.begin(), order.end(), [&](int a, int bb) { return rows[a] > rows[bb]; });
         rgb_tuning_t base = win;
-        if (base.variant == RGB_VARIANT_BATCHED) {
+        if (base.variant == RGB_VARIANT_BATCHED || base.variant == RGB_VARIANT_POOLED) {
             base = cur;
             base.variant = RGB_VARIANT_PERSISTENT;
         }
@@ -438,7 +464,7 @@ rgb_err_t rgb_autotune(rgb_ctx_t* ctx, int64_t num_lps, int64_t num_constraints,
                     cand.log2_lanes[c] = lg;
                     if ((r = try_cfg(cand)) != RGB_OK) return r;
                 }
-            if (win.variant != RGB_VARIANT_BATCHED) base = win;
+            if (win.variant == RGB_VARIANT_PERSISTENT || win.variant == RGB_VARIANT_BINNED) base = win;
         }
         // 4. queue share and chunk of the persistent kernel
         for (int share : {0, 128, 512, 1024})

@@ -114,10 +114,13 @@ __device__ __forceinline__ bool row_violates(float ax, float ay, float b, const 
     if (t != 0.0f) return t > 0.0f;
     if (st.kind == kCorner) return b < 0.0f;
     // row parallel to the ray's line: compare a.p0 with b in FP64,
-    // a.p0 = b_l (a.a_l) / |a_l|^2
-    double l2 = (double)st.lx * st.lx + (double)st.ly * st.ly;
-    double al = (double)ax * st.lx + (double)ay * st.ly;
-    return (double)st.lb * al > (double)b * l2;
+    // a.p0 = b_l (a.a_l) / |a_l|^2.  (The empty asm keeps this rare work in
+    // its branch instead of letting it be hoisted out of the scan loop.)
+    float lx = st.lx, ly = st.ly, lb = st.lb;
+    asm volatile("" : "+v"(lx), "+v"(ly), "+v"(lb));
+    double l2 = (double)lx * lx + (double)ly * ly;
+    double al = (double)ax * lx + (double)ay * ly;
+    return (double)lb * al > (double)b * l2;
 }
 
 __device__ __forceinline__ void make_line(Line& L, float lx, float ly, float lb) {
@@ -126,7 +129,9 @@ __device__ __forceinline__ void make_line(Line& L, float lx, float ly, float lb)
     L.lb = lb;
     L.ux = -ly;
     L.uy = lx;
-    float k = lb / __builtin_fmaf(lx, lx, ly * ly);
+    // p0 = b_l a_l / |a_l|^2 with a reciprocal (1 ulp): p0 only has to lie on
+    // the line to rounding, and every kernel computes it the same way
+    float k = lb * __builtin_amdgcn_rcpf(__builtin_fmaf(lx, lx, ly * ly));
     L.p0x = k * lx;
     L.p0y = k * ly;
     L.pscale = __builtin_fabsf(k);

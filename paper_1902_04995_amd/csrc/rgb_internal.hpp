@@ -55,5 +55,7 @@ int persist_blocks_per_cu();
 hipError_t launch_plain(const Problem& P, hipStream_t stream);
 hipError_t launch_group(const Problem& P, int lanes_per_lp, hipStream_t stream);
 bool group_supported(int lanes_per_lp);
+hipError_t launch_pool(const Problem& P, int lanes_per_lp, int rows_per_lane, int wait8, hipStream_t stream);
+bool pool_supported(int lanes_per_lp, int rows_per_lane);
 
 }  // namespace rgb

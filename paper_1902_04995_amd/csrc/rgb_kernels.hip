@@ -124,29 +124,61 @@ __device__ __forceinline__ float dpp_f(float v) {
 // Butterfly over aligned groups of 2^lg lanes: quad_perm xor 1 and xor 2,
 // row half-mirror (8), row mirror (16), swizzle swap 16 (32), then the other
 // half of the wave (64).  lg is wave-uniform; it is a constant wherever the
-// width is fixed at compile time.
-#define RGB_GROUP_REDUCE(NAME, T, OP, DPP)                                           \
-    __device__ __forceinline__ T NAME(T v, int lg) {                                 \
-        if (lg >= 1) v = OP(v, DPP<0xB1>(v));                                        \
-        if (lg >= 2) v = OP(v, DPP<0x4E>(v));                                        \
-        if (lg >= 3) v = OP(v, DPP<0x141>(v));                                       \
-        if (lg >= 4) v = OP(v, DPP<0x140>(v));                                       \
-        if (lg >= 5) {                                                               \
-            int s = __builtin_amdgcn_ds_swizzle(__builtin_bit_cast(int, v), 0x401F); \
-            v = OP(v, __builtin_bit_cast(T, s));                                     \
-        }                                                                            \
-        if (lg >= 6) v = OP(v, __shfl_xor(v, 32));                                   \
-        return v;                                                                    \
+// width is fixed at compile time.  The float steps inside a row are single
+// v_min/v_max instructions with a DPP source (bounds are never NaN, so the
+// IEEE NaN rules of fmin/fmax do not matter); `s_nop 1` supplies the two
+// wait states a DPP read needs after a VALU write of its source.
+#define RGB_DPP_FSTEP(NAME, OP, CTRL)                                                                   \
+    __device__ __forceinline__ float NAME(float v) {                                                    \
+        float r;                                                                                        \
+        asm volatile("s_nop 1\n\t" OP " %0, %1, %1 " CTRL " row_mask:0xf bank_mask:0xf bound_ctrl:1"     \
+                     : "=v"(r)                                                                          \
+                     : "v"(v));                                                                         \
+        return r;                                                                                       \
     }
+RGB_DPP_FSTEP(min_xor1, "v_min_f32_dpp", "quad_perm:[1,0,3,2]")
+RGB_DPP_FSTEP(min_xor2, "v_min_f32_dpp", "quad_perm:[2,3,0,1]")
+RGB_DPP_FSTEP(min_hmir, "v_min_f32_dpp", "row_half_mirror")
+RGB_DPP_FSTEP(min_mir, "v_min_f32_dpp", "row_mirror")
+RGB_DPP_FSTEP(max_xor1, "v_max_f32_dpp", "quad_perm:[1,0,3,2]")
+RGB_DPP_FSTEP(max_xor2, "v_max_f32_dpp", "quad_perm:[2,3,0,1]")
+RGB_DPP_FSTEP(max_hmir, "v_max_f32_dpp", "row_half_mirror")
+RGB_DPP_FSTEP(max_mir, "v_max_f32_dpp", "row_mirror")
+#undef RGB_DPP_FSTEP
 
-// bounds are never NaN, so a compare and select is an exact min/max
 __device__ __forceinline__ float fmin_(float a, float b) { return b < a ? b : a; }
 __device__ __forceinline__ float fmax_(float a, float b) { return b > a ? b : a; }
 __device__ __forceinline__ int imin_(int a, int b) { return a < b ? a : b; }
-RGB_GROUP_REDUCE(group_min, float, fmin_, dpp_f)
-RGB_GROUP_REDUCE(group_max, float, fmax_, dpp_f)
-RGB_GROUP_REDUCE(group_min_i, int, imin_, dpp_i)
-#undef RGB_GROUP_REDUCE
+
+__device__ __forceinline__ float group_min(float v, int lg) {
+    if (lg >= 1) v = min_xor1(v);
+    if (lg >= 2) v = min_xor2(v);
+    if (lg >= 3) v = min_hmir(v);
+    if (lg >= 4) v = min_mir(v);
+    if (lg >= 5) v = fmin_(v, __builtin_bit_cast(float, __builtin_amdgcn_ds_swizzle(__builtin_bit_cast(int, v), 0x401F)));
+    if (lg >= 6) v = fmin_(v, __shfl_xor(v, 32));
+    return v;
+}
+
+__device__ __forceinline__ float group_max(float v, int lg) {
+    if (lg >= 1) v = max_xor1(v);
+    if (lg >= 2) v = max_xor2(v);
+    if (lg >= 3) v = max_hmir(v);
+    if (lg >= 4) v = max_mir(v);
+    if (lg >= 5) v = fmax_(v, __builtin_bit_cast(float, __builtin_amdgcn_ds_swizzle(__builtin_bit_cast(int, v), 0x401F)));
+    if (lg >= 6) v = fmax_(v, __shfl_xor(v, 32));
+    return v;
+}
+
+__device__ __forceinline__ int group_min_i(int v, int lg) {
+    if (lg >= 1) v = imin_(v, dpp_i<0xB1>(v));
+    if (lg >= 2) v = imin_(v, dpp_i<0x4E>(v));
+    if (lg >= 3) v = imin_(v, dpp_i<0x141>(v));
+    if (lg >= 4) v = imin_(v, dpp_i<0x140>(v));
+    if (lg >= 5) v = imin_(v, __builtin_amdgcn_ds_swizzle(v, 0x401F));
+    if (lg >= 6) v = imin_(v, __shfl_xor(v, 32));
+    return v;
+}
 
 __device__ __forceinline__ uint64_t group_mask(int lg, int gbase) {
     return lg >= 6 ? ~0ull : (((1ull << (1 << lg)) - 1ull) << gbase);
@@ -189,6 +221,61 @@ __device__ __forceinline__ int group_find(const RowRef<WIDE>& R, int v, const Li
         best = (hit && h < best) ? h : best;
     }
     return group_min_i(best, lg);
+}
+
+// After the bounds of a 1D LP are known on every lane of the group: the
+// rare exact rerun (hi = -inf flags a parallel row or an overflow), the
+// parallel-row and near-tie decisions, then the new state.
+template <bool WIDE>
+__device__ __forceinline__ void settle_1dlp(LpState& st, const RowRef<WIDE>& R, int v, const Line& L, float hi,
+                                            float lo, float cx, float cy, int gl, int lg, uint64_t gmask) {
+    bool par = false;
+    if (hi == -__builtin_huge_valf()) {
+        hi = __builtin_huge_valf();
+        lo = -__builtin_huge_valf();
+        for (int h = gl; h < v; h += (1 << lg)) work_unit_exact(R.x(h), R.y(h), R.c(h), L, hi, lo, par);
+        hi = group_min(hi, lg);
+        lo = group_max(lo, lg);
+    }
+    par = (__ballot(par) & gmask) != 0;
+    if (par) {
+        set_dead(st, kInfeasible);
+        return;
+    }
+    bool inf = false;
+    if (!__builtin_isinf(hi) && !__builtin_isinf(lo)) {
+        inf = lo > hi;
+        if (near_tie(L, hi, lo)) {
+            int il = group_find(R, v, L, lo, false, gl, lg);
+            int ih = group_find(R, v, L, hi, true, gl, lg);
+            if (il != kNoIdx && ih != kNoIdx)
+                inf = exact_lo_gt_hi(L, R.x(il), R.y(il), R.c(il), R.x(ih), R.y(ih), R.c(ih));
+        }
+    }
+    if (inf) set_dead(st, kInfeasible);
+    else move_on_line(st, v, L, hi, lo, prefers_up(L, cx, cy));
+}
+
+// End of one LP on its group: an LP that died early still gets its remaining
+// rows checked for non-finite values, a vertex gets its second defining row,
+// and the group's first lane stores the result.
+template <bool WIDE>
+__device__ __forceinline__ void finish_group(const Problem& P, int64_t lp, int64_t start, const RowRef<WIDE>& R,
+                                             LpState& st, int cur, int m, bool bad, int n1d, int gl, int lg,
+                                             uint64_t gmask) {
+    if (lp >= 0 && st.kind == kDead && st.dead_status == kInfeasible)
+        for (int idx = cur + gl; idx < m; idx += (1 << lg)) bad |= !finite3(R.x(idx), R.y(idx), R.c(idx));
+    if ((__ballot(bad) & gmask) != 0) set_dead(st, kInvalid);
+    int h = -1;
+    if (__ballot(st.kind == kPoint) != 0) {
+        if (st.kind == kPoint) {
+            Line L;
+            make_line(L, R.x(st.l), R.y(st.l), R.c(st.l));
+            h = group_find(R, st.l, L, st.sig, st.up, gl, lg);
+            if (h == kNoIdx) h = st.l;  // cannot happen (the bound came from these bits); x is NaN then
+        }
+    }
+    if (lp >= 0 && gl == 0) finish_lp(P, lp, start, st, h, n1d);
 }
 
 // Solve the LP `lp` (-1: none) with a group of G = 2^lg lanes; every lane of
@@ -261,51 +348,13 @@ __device__ __forceinline__ void solve_group(const Problem& P, int64_t lp, int lg
                 for (int h = gl; h < v; h += G) work_unit(R.x(h), R.y(h), R.c(h), L, hi, lo);
                 hi = group_min(hi, lg);
                 lo = group_max(lo, lg);
-                bool par = false;
-                if (hi == -__builtin_huge_valf()) {  // rare: a row parallel to line v, or an overflow
-                    hi = __builtin_huge_valf();
-                    lo = -__builtin_huge_valf();
-                    for (int h = gl; h < v; h += G) work_unit_exact(R.x(h), R.y(h), R.c(h), L, hi, lo, par);
-                    hi = group_min(hi, lg);
-                    lo = group_max(lo, lg);
-                }
-                par = (__ballot(par) & gmask) != 0;
-                if (par) {
-                    set_dead(st, kInfeasible);
-                } else {
-                    bool inf = false;
-                    if (!__builtin_isinf(hi) && !__builtin_isinf(lo)) {
-                        inf = lo > hi;
-                        if (near_tie(L, hi, lo)) {
-                            int il = group_find(R, v, L, lo, false, gl, lg);
-                            int ih = group_find(R, v, L, hi, true, gl, lg);
-                            if (il != kNoIdx && ih != kNoIdx)
-                                inf = exact_lo_gt_hi(L, R.x(il), R.y(il), R.c(il), R.x(ih), R.y(ih), R.c(ih));
-                        }
-                    }
-                    if (inf) set_dead(st, kInfeasible);
-                    else move_on_line(st, v, L, hi, lo, prefers_up(L, cx, cy));
-                }
+                settle_1dlp(st, R, v, L, hi, lo, cx, cy, gl, lg, gmask);
             }
             cur = v + 1;
             if (cur >= m || st.kind == kDead) done = true;
         }
     }
-    // an LP that died early still gets its remaining rows checked for non-finite values
-    if (lp >= 0 && st.kind == kDead && st.dead_status == kInfeasible)
-        for (int idx = cur + gl; idx < m; idx += G) bad |= !finite3(R.x(idx), R.y(idx), R.c(idx));
-    if ((__ballot(bad) & gmask) != 0) set_dead(st, kInvalid);
-
-    int h = -1;
-    if (__ballot(st.kind == kPoint) != 0) {
-        if (st.kind == kPoint) {
-            Line L;
-            make_line(L, R.x(st.l), R.y(st.l), R.c(st.l));
-            h = group_find(R, st.l, L, st.sig, st.up, gl, lg);
-            if (h == kNoIdx) h = st.l;  // cannot happen (the bound came from these bits); x is NaN then
-        }
-    }
-    if (lp >= 0 && gl == 0) finish_lp(P, lp, start, st, h, n1d);
+    finish_group(P, lp, start, R, st, cur, m, bad, n1d, gl, lg, gmask);
 }
 
 template <int G, bool WIDE>
@@ -316,6 +365,271 @@ __global__ __launch_bounds__(256) void k_group(Problem P) {
     if (q < P.num_lps) lp = P.order ? (int64_t)P.order[q] : q;
     constexpr int LG = G == 4 ? 2 : G == 8 ? 3 : G == 16 ? 4 : G == 32 ? 5 : 6;
     solve_group<LG, WIDE>(P, lp);
+}
+
+// ---------------------------------------------------------------------------
+// pooled: small scan groups, work units pooled over the whole wave
+// ---------------------------------------------------------------------------
+// Groups of G = 4..16 lanes scan as in the group kernel, but a group that
+// finds a violated row waits until enough of the wave's groups wait too.
+// Then one round serves all of them: their work units (Sec. 3) are dealt to
+// the 64 lanes in proportion to each 1D LP's length, every lane folds its
+// units into running bounds, and the bounds meet in LDS through integer
+// min/max atomics on order-preserving keys (exact, like the paper's
+// shared-memory atomics).  The settling of the 1D LPs then runs once for all
+// waiting groups.  This amortises the fixed cost of a violation over up to
+// 16 LPs and keeps every lane busy however uneven the 1D LPs are.
+
+// Float <-> int key with the same order (no NaN ever reaches a bound).
+__device__ __forceinline__ int fkey(float f) {
+    int k = __builtin_bit_cast(int, f);
+    return k ^ ((k >> 31) & 0x7fffffff);
+}
+__device__ __forceinline__ float funkey(int k) { return __builtin_bit_cast(float, k ^ ((k >> 31) & 0x7fffffff)); }
+
+// Compiler-level ordering of LDS accesses between lanes of one wave (the LDS
+// executes one wave's instructions in order).
+__device__ __forceinline__ void wave_lds_order() { __atomic_signal_fence(__ATOMIC_SEQ_CST); }
+
+// One waiting group's 1D LP, as published to the wave.
+struct alignas(16) PoolRec {
+    int v;             // work units: rows 0 .. v-1 (0: none pooled)
+    int L, n;          // lanes L .. L+n-1 serve them
+    int hi, lo;        // bounds as keys, combined by atomics
+    uint32_t first_lo;  // row offset of the LP
+    int32_t first_hi;
+    int pad;
+    float p0x, p0y, ux, uy;
+};
+
+struct PoolLds {
+    int slot[64];  // lane -> group whose lanes start there, or -1
+    PoolRec g[16];
+};
+
+// Inclusive prefix sum over each row of 16 lanes.
+__device__ __forceinline__ int row_scan_i(int x) {
+    x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xF, 0xF, false);
+    x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xF, 0xF, false);
+    x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xF, 0xF, false);
+    x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xF, 0xF, false);
+    return x;
+}
+__device__ __forceinline__ float row_scan_f(float x) {
+    x += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x111, 0xF, 0xF, false));
+    x += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x112, 0xF, 0xF, false));
+    x += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x114, 0xF, 0xF, false));
+    x += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x118, 0xF, 0xF, false));
+    return x;
+}
+
+// The pooled work units of one round; all 64 lanes call this together after
+// the waiting groups published their records (v > 0 for at least one).
+template <bool WIDE>
+__device__ __forceinline__ void pool_work_units(const Problem& P, PoolLds& S, int K) {
+    const int lane = __lane_id();
+    // lanes t < K size the shares: group t gets 1 + floor(v_t (64 - k) / W)
+    // lanes, k groups taking part, W = sum of v_t.  The shares add up to at
+    // most 64 (the sum of the floors is at most 64 - k; FP32 rounding moves
+    // the sum by far less than one).
+    int vt = lane < K ? S.g[lane].v : 0;
+    float fv = (float)vt;
+    float W = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, row_scan_f(fv)), 15));
+    int k = __popcll(__ballot(lane < 16 && vt > 0));
+    float q = (float)(64 - k) * __builtin_amdgcn_rcpf(W);
+    int nt = vt > 0 ? 1 + (int)(fv * q) : 0;
+    int incl = row_scan_i(nt);
+    int Lt = incl - nt;
+    int ntot = __builtin_amdgcn_readlane(incl, 15);
+    ntot = ntot < 64 ? ntot : 64;
+    if (lane < K && nt > 0 && Lt < 64) {
+        S.g[lane].L = Lt;
+        S.g[lane].n = nt < 64 - Lt ? nt : 64 - Lt;
+        S.slot[Lt] = lane;
+    }
+    wave_lds_order();
+    int s = S.slot[lane];
+    uint64_t starts = __ballot(s >= 0);
+    if (lane < ntot) {
+        // this lane serves the group whose lanes start at the nearest start at or below it
+        int p = 63 - __builtin_clzll(starts & (~0ull >> (63 - lane)));
+        int g = __shfl(s, p);
+        const PoolRec& r = S.g[g];
+        int v = r.v, L0 = r.L, n = r.n;
+        typename std::conditional<WIDE, int64_t, uint32_t>::type first;
+        if constexpr (WIDE) first = (int64_t)(((uint64_t)(uint32_t)r.first_hi << 32) | r.first_lo);
+        else first = r.first_lo;
+        Line L;
+        L.p0x = r.p0x;
+        L.p0y = r.p0y;
+        L.ux = r.ux;
+        L.uy = r.uy;
+        RowRef<WIDE> R{P.ax, P.ay, P.b, first};
+        // four units per step with their loads issued together; indices past
+        // the end repeat row v-1, which cannot change a min or a max
+        float hi = __builtin_huge_valf(), lo = -__builtin_huge_valf();
+        for (int h = lane - L0; h < v; h += 4 * n) {
+            float x[4], y[4], c[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                int hk = h + k * n < v ? h + k * n : v - 1;
+                x[k] = R.x(hk);
+                y[k] = R.y(hk);
+                c[k] = R.c(hk);
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) work_unit(x[k], y[k], c[k], L, hi, lo);
+        }
+        if (hi != __builtin_huge_valf())
+            __hip_atomic_fetch_min(&S.g[g].hi, fkey(hi), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+        if (lo != -__builtin_huge_valf())
+            __hip_atomic_fetch_max(&S.g[g].lo, fkey(lo), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+    }
+    wave_lds_order();
+}
+
+// Solve the LP `lp` (-1: none) with a scan group of G = 2^lg lanes (lg 2..4)
+// and pooled 1D LPs; every lane of the wave calls this together, each group
+// with its own LP, and S is the wave's own LDS block.  A scan step tests RW
+// rows per lane (a window of RW G rows).  Scanning goes on while fewer than
+// wait8/8 of the live groups wait (wait8 = 0: serve every violation at once).
+template <int LGC, int RW, bool WIDE>
+__device__ __forceinline__ void solve_pool(const Problem& P, int64_t lp, int lg_rt, PoolLds& S, int wait8) {
+    const int lg = LGC >= 0 ? LGC : lg_rt;
+    const int G = 1 << lg;
+    const int K = 64 >> lg;
+    const int lane = __lane_id();
+    const int gl = lane & (G - 1);
+    const int gbase = lane & ~(G - 1);
+    const int grp = lane >> lg;
+    const uint64_t gmask = group_mask(lg, gbase);
+
+    int64_t start = 0;
+    int m = 0;
+    float cx = 0.0f, cy = 0.0f;
+    bool ok = false;
+    if (lp >= 0) {
+        cx = P.cx[lp];
+        cy = P.cy[lp];
+        ok = lp_range(P, lp, start, m) && __builtin_isfinite(cx) && __builtin_isfinite(cy);
+    }
+    RowRef<WIDE> R{P.ax, P.ay, P.b, (typename std::conditional<WIDE, int64_t, uint32_t>::type)start};
+
+    LpState st;
+    init_state(st, cx, cy);
+    if (lp >= 0 && !ok) set_dead(st, kInvalid);
+    bool done = lp < 0 || !ok || m == 0;
+    bool bad = false;
+    bool pend = false;  // a violated row waits for the next round
+    int cur = 0, v = 0;
+    int n1d = 0;
+    float vx = 0.0f, vy = 0.0f, vb = 0.0f;  // the waiting violated row
+
+    while (true) {
+        while (true) {
+            const bool scanning = !done && !pend;
+            const int nsc = __popcll(__ballot(scanning));
+            const int nwt = __popcll(__ballot(pend));
+            if (nsc == 0 || (nwt > 0 && nwt * 8 >= (nsc + nwt) * wait8)) break;
+            if (scanning) {
+                // window: rows cur + gl + k G, k < RW (cur < m here, so m - 1 is a row)
+                float tx[RW], ty[RW], tb[RW];
+                bool in[RW];
+#pragma unroll
+                for (int k = 0; k < RW; ++k) {
+                    int idx = cur + gl + k * G;
+                    in[k] = idx < m;
+                    int ld = in[k] ? idx : m - 1;
+                    tx[k] = R.x(ld);
+                    ty[k] = R.y(ld);
+                    tb[k] = R.c(ld);
+                }
+                bool any_np = false;
+#pragma unroll
+                for (int k = 0; k < RW; ++k) any_np |= in[k];
+                const bool all_point = __ballot(any_np && st.kind != kPoint) == 0;
+                uint64_t bsel = 0;
+                int ksel = RW;
+                float sx = 0.0f, sy = 0.0f, sb = 0.0f;
+#pragma unroll
+                for (int k = RW - 1; k >= 0; --k) {
+                    bool fin = finite3(tx[k], ty[k], tb[k]);
+                    bad |= in[k] && !fin;
+                    bool viol;
+                    if (all_point) viol = in[k] && point_violated(tx[k], ty[k], tb[k], st.px, st.py);
+                    else viol = in[k] && fin && row_violates(tx[k], ty[k], tb[k], st);
+                    uint64_t bk = __ballot(viol) & gmask;
+                    if (bk != 0) {
+                        bsel = bk;
+                        ksel = k;
+                        sx = tx[k];
+                        sy = ty[k];
+                        sb = tb[k];
+                    }
+                }
+                if (bsel == 0) {
+                    cur += RW * G;
+                    if (cur >= m) done = true;
+                } else {
+                    int src = __builtin_ctzll(bsel);
+                    v = cur + ksel * G + (src - gbase);
+                    vx = __shfl(sx, src);
+                    vy = __shfl(sy, src);
+                    vb = __shfl(sb, src);
+                    pend = true;
+                    ++n1d;
+                }
+            }
+        }
+        if (__ballot(pend) == 0) break;
+
+        // one round for every waiting group
+        const bool zero = vx == 0.0f && vy == 0.0f;  // 0 <= b with b < 0
+        Line L;
+        make_line(L, vx, vy, vb);
+        const bool part = pend && !zero && v > 0;
+        S.slot[lane] = -1;
+        if (gl == 0) {
+            PoolRec& r = S.g[grp];
+            r.v = part ? v : 0;
+            r.hi = fkey(__builtin_huge_valf());
+            r.lo = fkey(-__builtin_huge_valf());
+            if (part) {
+                r.first_lo = (uint32_t)R.first;
+                r.first_hi = WIDE ? (int32_t)((uint64_t)R.first >> 32) : 0;
+                r.p0x = L.p0x;
+                r.p0y = L.p0y;
+                r.ux = L.ux;
+                r.uy = L.uy;
+            }
+        }
+        wave_lds_order();
+        if (__ballot(part) != 0) pool_work_units<WIDE>(P, S, K);
+        if (pend) {
+            if (zero) {
+                set_dead(st, kInfeasible);
+            } else {
+                float hi = funkey(S.g[grp].hi), lo = funkey(S.g[grp].lo);
+                settle_1dlp(st, R, v, L, hi, lo, cx, cy, gl, lg, gmask);
+            }
+            cur = v + 1;
+            if (cur >= m || st.kind == kDead) done = true;
+            pend = false;
+        }
+        wave_lds_order();
+    }
+    finish_group(P, lp, start, R, st, cur, m, bad, n1d, gl, lg, gmask);
+}
+
+template <int G, int RW, bool WIDE>
+__global__ __launch_bounds__(256) void k_pool(Problem P, int wait8) {
+    __shared__ PoolLds pool[4];
+    constexpr int LPS_PER_BLOCK = 256 / G;
+    int64_t q = (int64_t)blockIdx.x * LPS_PER_BLOCK + threadIdx.x / G;
+    int64_t lp = -1;
+    if (q < P.num_lps) lp = P.order ? (int64_t)P.order[q] : q;
+    constexpr int LG = G == 4 ? 2 : G == 8 ? 3 : 4;
+    solve_pool<LG, RW, WIDE>(P, lp, 0, pool[threadIdx.x >> 6], wait8);
 }
 
 // ---------------------------------------------------------------------------
@@ -560,6 +874,37 @@ hipError_t launch_group(const Problem& P, int g, hipStream_t stream) {
         case 32: return launch_group_t<32>(P, stream);
         case 64: return launch_group_t<64>(P, stream);
         default: return hipErrorInvalidValue;
+    }
+}
+
+template <int G, int RW>
+static hipError_t launch_pool_t(const Problem& P, int wait8, hipStream_t stream) {
+    constexpr int LPS_PER_BLOCK = 256 / G;
+    int64_t blocks = (P.num_lps + LPS_PER_BLOCK - 1) / LPS_PER_BLOCK;
+    if (wide_rows(P))
+        hipLaunchKernelGGL((k_pool<G, RW, true>), dim3((unsigned)blocks), dim3(256), 0, stream, P, wait8);
+    else
+        hipLaunchKernelGGL((k_pool<G, RW, false>), dim3((unsigned)blocks), dim3(256), 0, stream, P, wait8);
+    return hipGetLastError();
+}
+
+bool pool_supported(int g, int rows) {
+    return (g == 4 || g == 8 || g == 16) && (rows == 1 || rows == 2 || rows == 4);
+}
+
+hipError_t launch_pool(const Problem& P, int g, int rows, int wait8, hipStream_t stream) {
+    if (P.num_lps == 0) return hipSuccess;
+    if (wait8 < 0 || wait8 > 8 || !pool_supported(g, rows)) return hipErrorInvalidValue;
+    switch (g * 8 + rows) {
+        case 4 * 8 + 1: return launch_pool_t<4, 1>(P, wait8, stream);
+        case 4 * 8 + 2: return launch_pool_t<4, 2>(P, wait8, stream);
+        case 4 * 8 + 4: return launch_pool_t<4, 4>(P, wait8, stream);
+        case 8 * 8 + 1: return launch_pool_t<8, 1>(P, wait8, stream);
+        case 8 * 8 + 2: return launch_pool_t<8, 2>(P, wait8, stream);
+        case 8 * 8 + 4: return launch_pool_t<8, 4>(P, wait8, stream);
+        case 16 * 8 + 1: return launch_pool_t<16, 1>(P, wait8, stream);
+        case 16 * 8 + 2: return launch_pool_t<16, 2>(P, wait8, stream);
+        default: return launch_pool_t<16, 4>(P, wait8, stream);
     }
 }
 

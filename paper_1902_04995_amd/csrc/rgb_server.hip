@@ -264,7 +264,7 @@ rgb_err_t rgb_server_create(rgb_ctx_t* ctx, const rgb_server_opts_t* opts, rgb_s
     if (o.max_batch_lps == 0) o.max_batch_lps = 65536;
     if (o.max_pending == 0) o.max_pending = 65536;
     if (o.n_streams < 1 || o.n_streams > 16 || o.max_batch_lps < 1 || o.max_pending < 1 ||
-        o.variant < RGB_VARIANT_AUTO || o.variant > RGB_VARIANT_BINNED || o.hbm_budget < 4096)
+        o.variant < RGB_VARIANT_AUTO || o.variant > RGB_VARIANT_POOLED || o.hbm_budget < 4096)
         return RGB_ERR_INVALID_ARG;
     int prev = 0;
     if (hipGetDevice(&prev) != hipSuccess) return RGB_ERR_DEVICE;

@@ -17,9 +17,12 @@ from paper_1902_04995_amd import gen
 
 pytestmark = pytest.mark.gpu
 
-# (variant, lanes_per_lp, slots) combinations exercised; (0, 0) = library default
+# (variant, lanes_per_lp, pool_wait) combinations exercised; 0 = library default
 SHAPES = [("plain", 0, 0), ("batched", 0, 0), ("batched", 4, 0), ("batched", 8, 0), ("batched", 16, 0),
-          ("batched", 32, 0), ("batched", 64, 0), ("persistent", 0, 0)]
+          ("batched", 32, 0), ("batched", 64, 0), ("persistent", 0, 0), ("pooled", 0, 0), ("pooled", 8, -1),
+          ("pooled", 16, 8), ("pooled", 4, 2)]
+# pooled kernels by (lanes_per_lp, rows per lane), all at the default wait
+POOL_SHAPES = [(g, r) for g in (4, 8, 16) for r in (1, 2, 4)]
 
 
 def _say(*a):
@@ -36,10 +39,10 @@ def rgb():
     return rgb
 
 
-def _run(rgb, bt, variant, g=0, s=0, n1d=False):
+def _run(rgb, bt, variant, g=0, s=0, n1d=False, rows=0):
     import torch
     dev = rgb.DeviceBatch(bt, "cuda:0")
-    out = dev.solve(variant=variant, lanes_per_lp=g, slots=s, want_n_1dlp=n1d)
+    out = dev.solve(variant=variant, lanes_per_lp=g, pool_wait=s, pool_rows=rows, want_n_1dlp=n1d)
     torch.cuda.synchronize()
     out = [t.cpu().numpy() for t in out]
     return [out[2], out[0], out[1]] + out[3:]   # status, x, y[, n_1dlp]
@@ -85,12 +88,29 @@ def test_parity_vs_oracle(rgb, oracle_lib, case):
                     f"{case}: {variant}/{g}x{s} differs from plain in {name}"
 
 
+@pytest.mark.parametrize("case", ["tiny_random", "tiny_int_boxed", "uniform_small", "uneven_small", "crowd_small"])
+def test_pool_shapes_match_plain(rgb, oracle_lib, case):
+    """Every pooled (lanes, rows per lane) instance against the oracle and,
+    bit for bit, against the plain kernel."""
+    bt = CASES[case]()
+    ref = oracle_lib.solve(bt)
+    base = _run(rgb, bt, "plain", n1d=True)
+    for g, r in POOL_SHAPES:
+        for w in (-1, 0, 8):
+            _say(f"[gpu] case={case} pooled G={g} R={r} W={w}")
+            got = _run(rgb, bt, "pooled", g, w, n1d=True, rows=r)
+            _check(bt, ref, got, f"{case}/pooled/{g}x{r}/w{w}")
+            for a, b_, name in zip(got, base, ("status", "x", "y", "n_1dlp")):
+                assert np.array_equal(a, b_, equal_nan=True) if a.dtype.kind == "f" else np.array_equal(a, b_), \
+                    f"{case}: pooled {g}x{r} w{w} differs from plain in {name}"
+
+
 def test_parity_tiny_integer_degenerate(rgb, oracle_lib):
     """Integer LPs are full of exact ties (concurrent and coincident lines,
     single-point regions); the exact guards must reproduce the exact answer."""
     bt = gen.tiny_integer_batch(4000, m_max=10, K=4, seed=4)
     ref = oracle_lib.solve(bt)
-    for variant, g, s in (("plain", 0, 0), ("batched", 4, 0), ("batched", 64, 0)):
+    for variant, g, s in (("plain", 0, 0), ("batched", 4, 0), ("batched", 64, 0), ("pooled", 4, -1), ("pooled", 16, 8)):
         _say(f"[gpu] case=tiny_int variant={variant} G={g} S={s}")
         _check(bt, ref, _run(rgb, bt, variant, g, s), f"tiny_int/{variant}")
 
@@ -101,7 +121,7 @@ def test_edge_cases(rgb, oracle_lib):
     dev = torch.device("cuda:0")
     z64 = torch.zeros(1, dtype=torch.int64, device=dev)
     e32 = torch.empty(0, dtype=torch.float32, device=dev)
-    for variant in ("plain", "batched", "persistent"):
+    for variant in ("plain", "batched", "persistent", "binned", "pooled"):
         x, y, st = rgb.solve_batch(z64, e32, e32, e32, e32, e32, variant=variant)
         assert x.numel() == 0
     # LPs with no rows, NaN / inf rows and objectives, zero normals
@@ -133,7 +153,7 @@ def test_malformed_offsets_are_invalid_not_read(rgb):
     c = torch.ones(4, dtype=torch.float32, device=dev)
     # LP0 fine, LP1 decreasing, LP2 past the end, LP3 decreasing
     offs = torch.tensor([0, 4, 2, 100, 8], dtype=torch.int64, device=dev)
-    for variant in ("plain", "batched", "persistent"):
+    for variant in ("plain", "batched", "persistent", "binned", "pooled"):
         _say(f"[gpu] case=malformed variant={variant}")
         x, y, st = rgb.solve_batch(offs, ax, ax, ax, c, c, variant=variant)
         torch.cuda.synchronize()
@@ -151,13 +171,14 @@ def test_sizes_around_group_widths(rgb, oracle_lib, m):
         _check(bt, ref, _run(rgb, bt, variant, g, s), f"overflow{m}/{variant}/{g}x{s}")
 
 
+@pytest.mark.parametrize("variant", ["persistent", "pooled"])
 @pytest.mark.parametrize("name", ["uniform", "uneven", "crowd"])
-def test_full_size_sampled(rgb, oracle_lib, name):
-    """Full-size workloads in the launch the benchmark times (persistent),
-    checked on a sample of LPs the oracle solves one by one."""
+def test_full_size_sampled(rgb, oracle_lib, name, variant):
+    """Full-size workloads in the launches the benchmark times, checked on a
+    sample of LPs the oracle solves one by one."""
     bt = gen.make_config(name, seed=0)
-    _say(f"[gpu] case=full {name} lps={bt.num_lps} rows={bt.num_constraints}")
-    got = _run(rgb, bt, "persistent")
+    _say(f"[gpu] case=full {name} variant={variant} lps={bt.num_lps} rows={bt.num_constraints}")
+    got = _run(rgb, bt, variant)
     rng = np.random.default_rng(1)
     idx = np.sort(rng.choice(bt.num_lps, size=min(4000, bt.num_lps), replace=False))
     sub = bt.subset(idx)

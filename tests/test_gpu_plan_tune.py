@@ -38,7 +38,7 @@ def test_tuning_roundtrip_and_validation(rgb):
     ctx = rgb.Context(0)
     t = ctx.tuning
     d = t.to_dict()
-    assert d["variant"] in ("persistent", "binned", "batched")
+    assert d["variant"] in ("persistent", "binned", "batched", "pooled")
     d["batched_lanes"] = 32
     d["log2_lanes"][9] = 4
     ctx.tuning = d
@@ -61,7 +61,7 @@ def test_autotune_keeps_results(rgb, oracle_lib, which):
     ctx = rgb.Context(0)
     _say(f"[gpu] autotune {which}")
     best = dev.autotune(reps=2, budget_ms=1500.0, ctx=ctx)
-    assert best.ms > 0 and best.variant in (2, 3, 4)
+    assert best.ms > 0 and best.variant in (2, 3, 4, 5)
     assert ctx.tuning.to_dict() == best.to_dict()
     _say(f"[gpu] tuned: {best.to_dict()}")
     got = _host(dev.solve(variant="auto", ctx=ctx))
@@ -75,7 +75,7 @@ def test_autotune_keeps_results(rgb, oracle_lib, which):
     ctx.close()
 
 
-@pytest.mark.parametrize("variant", ["persistent", "binned", "batched", "plain"])
+@pytest.mark.parametrize("variant", ["persistent", "binned", "batched", "pooled", "plain"])
 def test_plan_replays_match_eager(rgb, variant):
     import torch
     bt = gen.uneven_batch(2000, 8, 1500, seed=11)

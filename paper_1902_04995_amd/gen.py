@@ -358,6 +358,45 @@ def tiny_random_batch(num_lps: int, m_max: int = 40, seed: int = 0, m_min: int =
 
 # Named workloads.  ``scale`` shrinks the LP count for parity tests the oracle
 # finishes in seconds; scale=1 is the full size.
+def device_disk_batch(num_lps: int, m: int, seed: int, device="cuda"):
+    """A batch built directly in device memory (for sizes the host should not
+    generate): LP k has rows m*k .. m*k+m-1 with unit normals (cos t, sin t),
+    t ~ U[0, 2 pi), offsets b ~ U[1, 2] (so every LP contains the unit disk)
+    and a random unit objective.  Seeded torch generator on the device;
+    returns (offsets, ax, ay, b, cx, cy) tensors."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    n = num_lps * m
+    t = torch.rand(n, generator=g, device=device) * (2.0 * np.pi)
+    ax = torch.cos(t)
+    ay = torch.sin(t)
+    del t
+    b = torch.rand(n, generator=g, device=device) + 1.0
+    u = torch.rand(num_lps, generator=g, device=device) * (2.0 * np.pi)
+    cx, cy = torch.cos(u), torch.sin(u)
+    offsets = torch.arange(num_lps + 1, device=device, dtype=torch.int64) * m
+    return offsets, ax, ay, b, cx, cy
+
+
+def host_subset(offsets, ax, ay, b, cx, cy, idx) -> Batch:
+    """Copy the LPs `idx` of a device batch (tensors as from device_disk_batch)
+    into a host Batch."""
+    import torch
+    idx = np.asarray(idx, dtype=np.int64)
+    lo = offsets[torch.as_tensor(idx, device=offsets.device)].cpu().numpy()
+    hi = offsets[torch.as_tensor(idx + 1, device=offsets.device)].cpu().numpy()
+    sizes = hi - lo
+    out_offs = np.zeros(len(idx) + 1, dtype=np.int64)
+    np.cumsum(sizes, out=out_offs[1:])
+    gather = np.repeat(lo - out_offs[:-1], sizes) + np.arange(out_offs[-1], dtype=np.int64)
+    gi = torch.as_tensor(gather, device=ax.device)
+    pick = lambda t: t[gi].cpu().numpy().astype(np.float32)
+    ti = torch.as_tensor(idx, device=cx.device)
+    return Batch(out_offs, pick(ax), pick(ay), pick(b), cx[ti].cpu().numpy().astype(np.float32),
+                 cy[ti].cpu().numpy().astype(np.float32), np.full(len(idx), KIND_OTHER, np.int8), "device[subset]")
+
+
 CONFIGS = {
     "plain": dict(kind="uniform", num_lps=1024, m=64, infeasible_frac=0.0, unbounded_frac=0.0),
     "uniform": dict(kind="uniform", num_lps=131072, m=256),

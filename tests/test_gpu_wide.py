@@ -1,0 +1,55 @@
+"""GPU: a batch of more than 2^30 rows, which takes the kernels' 64-bit row
+indexing (every other test stays below it).  The batch is generated in device
+memory (~13 GB); all kernel families must agree bit for bit, and a sample of
+LPs is checked against the oracle."""
+import sys
+
+import numpy as np
+import pytest
+
+import lpcheck
+from paper_1902_04995_amd import gen
+
+pytestmark = pytest.mark.gpu
+
+M = 256
+B = (1 << 22) + 1  # B * M = 2^30 + 256 rows
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def test_more_than_2_30_rows(oracle_lib):
+    import torch
+    assert torch.cuda.is_available()
+    import paper_1902_04995_amd as rgb
+    free, _ = torch.cuda.mem_get_info()
+    need = 3 * 4 * B * M + 64 * B
+    if free < need + (2 << 30):
+        pytest.skip(f"needs {need / 2**30:.1f} GiB of free device memory, {free / 2**30:.1f} free")
+    _say(f"[gpu] case=wide lps={B} rows={B * M}")
+    offsets, ax, ay, b, cx, cy = gen.device_disk_batch(B, M, seed=30)
+    assert ax.numel() > (1 << 30)
+    torch.cuda.synchronize()
+    results = {}
+    for variant, g in (("plain", 0), ("batched", 32), ("persistent", 0), ("binned", 0), ("pooled", 8)):
+        _say(f"[gpu] case=wide variant={variant} G={g}")
+        x, y, st = rgb.solve_batch(offsets, ax, ay, b, cx, cy, variant=variant, lanes_per_lp=g)
+        torch.cuda.synchronize()
+        results[variant] = (st.cpu().numpy(), x.cpu().numpy(), y.cpu().numpy())
+        del x, y, st
+    base = results["plain"]
+    for variant, got in results.items():
+        for a, r, name in zip(got, base, ("status", "x", "y")):
+            assert np.array_equal(a, r, equal_nan=True), f"{variant} differs from plain in {name}"
+    # sample, including the LPs whose rows sit past row 2^30
+    rng = np.random.default_rng(3)
+    idx = np.unique(np.concatenate([rng.choice(B, 1500, replace=False), np.arange(B - 40, B)]))
+    sub = gen.host_subset(offsets, ax, ay, b, cx, cy, idx)
+    ref = oracle_lib.solve(sub)
+    st, x, y = (a[idx] for a in base)
+    bs, bx = lpcheck.compare(st, x.astype(np.float64), y.astype(np.float64), ref["status"], ref["x"], ref["y"])
+    assert len(bs) == 0 and len(bx) == 0, (len(bs), len(bx))
+    assert np.all(st == 0)  # every LP contains the unit disk and has 256 spread normals

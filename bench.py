@@ -70,7 +70,7 @@ def served_leg(rgb, gen, n_requests, load, pool_size=96, seed=0):
             while time.perf_counter() - t0 < t_arr:
                 pass
             t_sub = time.perf_counter() - t0
-            tickets.append((srv.submit(pool[k]), t_sub - t_arr, k))
+            tickets.append((srv.submit(pool[k], wait=True), t_sub - t_arr, k))
         lat = []
         for t, lag, k in tickets:
             _, _, _, ms = srv.wait(t)
@@ -82,14 +82,15 @@ def served_leg(rgb, gen, n_requests, load, pool_size=96, seed=0):
                 "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
                 "max_ms": float(lat.max())}
 
-    served = rgb.Server(n_streams=4, max_batch_lps=16384, hbm_budget=4 << 30)
-    fifo = rgb.Server(n_streams=1, one_request_per_batch=True, variant="plain", hbm_budget=4 << 30)
+    served = rgb.Server(n_streams=4, max_batch_lps=16384, hbm_budget=4 << 30, host_ring_mib=1024)
+    fifo = rgb.Server(n_streams=1, one_request_per_batch=True, variant="plain", hbm_budget=4 << 30,
+                      host_ring_mib=1024)
     # warm-up (pinned buffers, workspaces) and capacity from a burst of the whole pool
     for srv in (served, fifo):
-        for t in [srv.submit(r) for r in pool[:8]]:
+        for t in [srv.submit(r, wait=True) for r in pool[:8]]:
             srv.wait(t)
     t0 = time.perf_counter()
-    for t in [served.submit(r) for r in pool]:
+    for t in [served.submit(r, wait=True) for r in pool]:
         served.wait(t)
     capacity = float(lps.sum()) / (time.perf_counter() - t0)
     order = rng.integers(0, pool_size, n_requests)

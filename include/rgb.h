@@ -190,14 +190,16 @@ rgb_err_t rgb_plan_destroy(rgb_plan_t* plan);
  *
  * A server owns a device arena of `hbm_budget` bytes, its own context (with
  * the creating context's tuning), `n_streams` streams and one scheduler
- * thread.  Requests are submitted from host memory and queued; the scheduler
- * admits them in arrival order into micro-batches as soon as a stream is free
- * and the arena has room (a request that arrives while others are on the GPU
- * joins the next micro-batch, and micro-batches on different streams overlap
- * on the device), copies each micro-batch through pinned memory into the
- * arena, solves it with rgb_solve_batch, copies the results back and frees
- * the arena block.  Results are exactly those of solving each request alone.
- * All calls are thread-safe.
+ * thread.  A submitted request is copied once, into pinned host rings
+ * (`host_ring_mib`, three quarters for rows at 12 B, a quarter for LPs at
+ * 16 B), and queued; the scheduler admits queued requests in arrival order
+ * into micro-batches as soon as a stream is free and the arena has room (a
+ * request that arrives while others are on the GPU joins the next
+ * micro-batch, and micro-batches on different streams overlap on the
+ * device), copies each micro-batch's ring spans straight into the arena,
+ * solves it with rgb_solve_batch, copies the results back and frees the arena
+ * block and the ring space.  Results are exactly those of solving each
+ * request alone.  All calls are thread-safe.
  * ------------------------------------------------------------------------- */
 typedef struct rgb_server rgb_server_t;
 
@@ -208,7 +210,7 @@ typedef struct {
     int32_t max_pending;           /* queued, not yet admitted requests; 0 = 65536 */
     int32_t variant;               /* kernel family of the micro-batches; AUTO = the tuning */
     int32_t one_request_per_batch; /* 1: every micro-batch holds a single request (no batching) */
-    int32_t reserved;
+    int32_t host_ring_mib;         /* pinned host memory holding queued requests, MiB; 0 = 256 */
 } rgb_server_opts_t;
 
 typedef struct {
@@ -225,8 +227,9 @@ rgb_err_t rgb_server_create(rgb_ctx_t* ctx, const rgb_server_opts_t* opts, rgb_s
 /* Queue one request.  Pointers are HOST memory in the layout of
  * rgb_solve_batch and are copied before the call returns.  *ticket receives
  * the request's id.  Errors: INVALID_ARG; TOO_LARGE if the request can never
- * fit (more LPs than max_batch_lps, or more bytes than the arena);
- * BUSY if max_pending requests are already queued (retry later). */
+ * fit (more LPs than max_batch_lps, more bytes than the arena, or more than
+ * the host rings hold); BUSY if max_pending requests are already queued or
+ * the host rings are full (retry later). */
 rgb_err_t rgb_server_submit(rgb_server_t* srv, int64_t num_lps, int64_t num_constraints, const int64_t* offsets,
                             const float* ax, const float* ay, const float* b, const float* cx, const float* cy,
                             uint64_t* ticket);

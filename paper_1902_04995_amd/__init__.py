@@ -16,6 +16,7 @@ from __future__ import annotations
 import ctypes
 import os
 import threading
+import time
 
 OPTIMAL, INFEASIBLE, UNBOUNDED, INVALID = 0, 1, 2, 3
 VARIANTS = {"auto": 0, "plain": 1, "batched": 2, "persistent": 3, "binned": 4, "pooled": 5}
@@ -73,7 +74,7 @@ class Tuning(ctypes.Structure):
 class _ServerOpts(ctypes.Structure):
     _fields_ = [("hbm_budget", ctypes.c_uint64), ("n_streams", ctypes.c_int32), ("max_batch_lps", ctypes.c_int32),
                 ("max_pending", ctypes.c_int32), ("variant", ctypes.c_int32), ("one_request_per_batch", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("host_ring_mib", ctypes.c_int32)]
 
 
 class _ServerStats(ctypes.Structure):
@@ -344,7 +345,7 @@ class Server:
     memory (numpy arrays), results go back to host memory."""
 
     def __init__(self, ctx: Context | None = None, *, hbm_budget=0, n_streams=0, max_batch_lps=0, max_pending=0,
-                 variant="auto", one_request_per_batch=False):
+                 variant="auto", one_request_per_batch=False, host_ring_mib=0):
         self.ctx = ctx or context(0)
         o = _ServerOpts()
         o.hbm_budget = int(hbm_budget)
@@ -353,6 +354,7 @@ class Server:
         o.max_pending = int(max_pending)
         o.variant = VARIANTS[variant] if isinstance(variant, str) else int(variant)
         o.one_request_per_batch = 1 if one_request_per_batch else 0
+        o.host_ring_mib = int(host_ring_mib)
         h = ctypes.c_void_p()
         rc = lib().rgb_server_create(self.ctx.handle, ctypes.byref(o), ctypes.byref(h))
         if rc != 0:
@@ -360,17 +362,24 @@ class Server:
         self.handle = h
         self._sizes = {}
 
-    def submit(self, batch) -> int:
-        """Queue a gen.Batch-like request; returns its ticket."""
+    def submit(self, batch, wait=False) -> int:
+        """Queue a gen.Batch-like request; returns its ticket.  With wait=True
+        a full queue or full host rings are waited out instead of raising
+        ServerBusy."""
         import numpy as np
         arrs = [np.ascontiguousarray(batch.offsets, dtype=np.int64)] + \
                [np.ascontiguousarray(getattr(batch, f), dtype=np.float32) for f in ("ax", "ay", "b", "cx", "cy")]
         B = arrs[0].shape[0] - 1
         N = arrs[1].shape[0]
         t = ctypes.c_uint64()
-        rc = lib().rgb_server_submit(self.handle, B, N, *[ctypes.c_void_p(a.ctypes.data) for a in arrs], ctypes.byref(t))
+        ptrs = [ctypes.c_void_p(a.ctypes.data) for a in arrs]
+        while True:
+            rc = lib().rgb_server_submit(self.handle, B, N, *ptrs, ctypes.byref(t))
+            if rc != ERR_BUSY or not wait:
+                break
+            time.sleep(50e-6)
         if rc == ERR_BUSY:
-            raise ServerBusy("server queue full")
+            raise ServerBusy("server queue or host rings full")
         if rc == ERR_TOO_LARGE:
             raise RequestTooLarge(f"request of {B} LPs / {N} rows can never fit")
         if rc != 0:

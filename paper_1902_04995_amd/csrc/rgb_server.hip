@@ -1,11 +1,12 @@
 // Served mode: continuous batching of LP requests over the solver ABI.
 //
-// Requests are copied in at submit time and queued.  One scheduler thread
-// owns every HIP call: it retires finished micro-batches (event polling),
-// then, for each idle stream, takes queued requests in arrival order into a
-// micro-batch while the LP cap and the arena's largest free block allow,
-// stages the micro-batch through the stream's pinned buffer into one arena
-// block, solves it with rgb_solve_batch and copies the results back.
+// rgb_server_submit copies a request once, into pinned host rings (one per
+// input array), and queues it.  One scheduler thread owns every HIP call: it
+// retires finished micro-batches (event polling), then, for each idle stream,
+// takes queued requests in arrival order into a micro-batch while they sit
+// next to each other in the rings and the LP cap and the arena's largest free
+// block allow, copies the rings' spans straight into one arena block, solves
+// it with rgb_solve_batch and copies the results back.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -23,6 +24,7 @@
 
 #include "../../include/rgb.h"
 #include "arena.hpp"
+#include "ring.hpp"
 #include "rgb_internal.hpp"
 
 namespace {
@@ -34,8 +36,9 @@ enum ReqState { kQueued = 0, kAdmitted = 1, kDone = 2, kFailed = 3 };
 struct Request {
     uint64_t id = 0;
     int64_t B = 0, N = 0;
-    std::vector<int64_t> offsets;
-    std::vector<float> ax, ay, b, cx, cy;
+    int64_t row_pos = 0, lp_pos = 0;  // first positions in the row and LP rings
+    uint64_t row_blk = 0, lp_blk = 0;  // ring block ids
+    bool ready = false;                // inputs copied into the rings
     std::vector<float> x, y;
     std::vector<int32_t> st;
     Clock::time_point t_submit, t_done;
@@ -64,11 +67,13 @@ struct Layout {
     }
 };
 
+// Pinned buffer of a stream: the micro-batch's offsets on the way in, its
+// x, y and status on the way out (the output part of Layout).
 struct Slot {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
-    char* pinned = nullptr;
-    size_t pinned_cap = 0;
+    char* pinned = nullptr;  // offsets: 8 (cap + 1) bytes, then the outputs
+    size_t out_at = 0;       // where the outputs start in `pinned`
     bool busy = false;
     uint64_t arena_off = 0;
     int64_t B = 0, N = 0;
@@ -84,6 +89,12 @@ struct rgb_server {
     char* arena_mem = nullptr;
     rgb::Arena arena;
     std::vector<Slot> slots;
+    // pinned request rings: rows (ax, ay, b) and LPs (cx, cy, end offset of
+    // each LP relative to its request)
+    char* ring_mem = nullptr;
+    float *r_ax = nullptr, *r_ay = nullptr, *r_b = nullptr, *r_cx = nullptr, *r_cy = nullptr;
+    int64_t* r_end = nullptr;
+    rgb::Ring rows, lps;
 
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
@@ -104,11 +115,13 @@ bool rgb_server::retire(Slot& s) {
     hipError_t q = hipEventQuery(s.done);
     if (q == hipErrorNotReady) return false;
     Layout L(s.B, s.N);
-    const char* out = s.pinned;
+    const char* out = s.pinned + s.out_at - L.x;  // outputs at the same offsets as in the arena block
     std::lock_guard<std::mutex> lk(mu);
     auto now = Clock::now();
     int64_t k = 0;
     for (Request* r : s.reqs) {
+        rows.release(r->row_blk);
+        lps.release(r->lp_blk);
         if (q == hipSuccess) {
             std::memcpy(r->x.data(), out + L.x + 4 * k, 4 * (size_t)r->B);
             std::memcpy(r->y.data(), out + L.y + 4 * k, 4 * (size_t)r->B);
@@ -140,7 +153,12 @@ bool rgb_server::launch(Slot& s) {
         const uint64_t room = arena.largest_free();
         while (!queue.empty()) {
             Request* r = queue.front();
+            if (!r->ready) break;
             if (opts.one_request_per_batch && !s.reqs.empty()) break;
+            if (!s.reqs.empty()) {  // a micro-batch is one span of each ring
+                const Request* p = s.reqs.back();
+                if (r->row_pos != p->row_pos + p->N || r->lp_pos != p->lp_pos + p->B) break;
+            }
             if (B + r->B > cap) break;
             if (arena.rounded(Layout(B + r->B, N + r->N).total) > room) break;
             queue.pop_front();
@@ -164,32 +182,28 @@ bool rgb_server::launch(Slot& s) {
     }
     Layout L(B, N);
     bool ok = true;
-    if (s.pinned_cap < L.total) {
-        if (s.pinned) (void)hipHostFree(s.pinned);
-        s.pinned = nullptr;
-        s.pinned_cap = 0;
-        size_t want = std::max(L.total, (size_t)1 << 20);
-        if (hipHostMalloc((void**)&s.pinned, want, hipHostMallocDefault) == hipSuccess) s.pinned_cap = want;
-        else ok = false;
-    }
-    if (ok) {
-        // stage: offsets shifted by each request's first row, then the arrays back to back
-        char* p = s.pinned;
-        int64_t* offs = reinterpret_cast<int64_t*>(p + L.offsets);
+    {
+        // offsets of the micro-batch: each request's LP ends shifted by its first row
+        int64_t* offs = reinterpret_cast<int64_t*>(s.pinned);
+        offs[0] = 0;
         int64_t lp = 0, row = 0;
         for (Request* r : s.reqs) {
-            for (int64_t k = 0; k < r->B; ++k) offs[lp + k] = row + r->offsets[k];
-            std::memcpy(p + L.cx + 4 * lp, r->cx.data(), 4 * (size_t)r->B);
-            std::memcpy(p + L.cy + 4 * lp, r->cy.data(), 4 * (size_t)r->B);
-            std::memcpy(p + L.ax + 4 * row, r->ax.data(), 4 * (size_t)r->N);
-            std::memcpy(p + L.ay + 4 * row, r->ay.data(), 4 * (size_t)r->N);
-            std::memcpy(p + L.b + 4 * row, r->b.data(), 4 * (size_t)r->N);
+            const int64_t* e = r_end + r->lp_pos;
+            for (int64_t k = 0; k < r->B; ++k) offs[lp + k + 1] = row + e[k];
             lp += r->B;
             row += r->N;
         }
-        offs[lp] = row;
+        const Request* f = s.reqs.front();
         char* d = arena_mem + off;
-        ok = hipMemcpyAsync(d, p, L.in_bytes, hipMemcpyHostToDevice, s.stream) == hipSuccess;
+        auto h2d = [&](size_t at, const void* src, size_t bytes) {
+            if (ok && bytes) ok = hipMemcpyAsync(d + at, src, bytes, hipMemcpyHostToDevice, s.stream) == hipSuccess;
+        };
+        h2d(L.offsets, offs, 8 * (size_t)(B + 1));
+        h2d(L.cx, r_cx + f->lp_pos, 4 * (size_t)B);
+        h2d(L.cy, r_cy + f->lp_pos, 4 * (size_t)B);
+        h2d(L.ax, r_ax + f->row_pos, 4 * (size_t)N);
+        h2d(L.ay, r_ay + f->row_pos, 4 * (size_t)N);
+        h2d(L.b, r_b + f->row_pos, 4 * (size_t)N);
         if (ok) {
             rgb_solve_opts_t so{};
             so.variant = opts.variant;
@@ -200,7 +214,9 @@ bool rgb_server::launch(Slot& s) {
                                  reinterpret_cast<float*>(d + L.y), reinterpret_cast<int32_t*>(d + L.st), &so,
                                  s.stream) == RGB_OK;
         }
-        if (ok) ok = hipMemcpyAsync(p + L.x, d + L.x, L.total - L.x, hipMemcpyDeviceToHost, s.stream) == hipSuccess;
+        if (ok)
+            ok = hipMemcpyAsync(s.pinned + s.out_at, d + L.x, L.total - L.x, hipMemcpyDeviceToHost, s.stream) ==
+                 hipSuccess;
         if (ok) ok = hipEventRecord(s.done, s.stream) == hipSuccess;
     }
     s.arena_off = off;
@@ -211,6 +227,8 @@ bool rgb_server::launch(Slot& s) {
         (void)hipStreamSynchronize(s.stream);
         std::lock_guard<std::mutex> lk(mu);
         for (Request* r : s.reqs) {
+            rows.release(r->row_blk);
+            lps.release(r->lp_blk);
             r->state = kFailed;
             r->t_done = Clock::now();
             stats.completed++;
@@ -263,7 +281,9 @@ rgb_err_t rgb_server_create(rgb_ctx_t* ctx, const rgb_server_opts_t* opts, rgb_s
     if (o.n_streams == 0) o.n_streams = 4;
     if (o.max_batch_lps == 0) o.max_batch_lps = 65536;
     if (o.max_pending == 0) o.max_pending = 65536;
-    if (o.n_streams < 1 || o.n_streams > 16 || o.max_batch_lps < 1 || o.max_pending < 1 ||
+    if (o.host_ring_mib == 0) o.host_ring_mib = 256;
+    if (o.n_streams < 1 || o.n_streams > 16 || o.max_batch_lps < 1 || o.max_pending < 1 || o.host_ring_mib < 1 ||
+        o.host_ring_mib > (1 << 20) ||
         o.variant < RGB_VARIANT_AUTO || o.variant > RGB_VARIANT_POOLED || o.hbm_budget < 4096)
         return RGB_ERR_INVALID_ARG;
     int prev = 0;
@@ -290,10 +310,33 @@ rgb_err_t rgb_server_create(rgb_ctx_t* ctx, const rgb_server_opts_t* opts, rgb_s
         return RGB_ERR_OOM;
     }
     s->arena = rgb::Arena(o.hbm_budget, 256);
+    // request rings: three quarters of the pinned bytes for rows (12 B each),
+    // a quarter for LPs (16 B each)
+    const size_t ring_bytes = (size_t)o.host_ring_mib << 20;
+    const int64_t n_rows = (int64_t)(ring_bytes / 4 * 3 / 12), n_lps = (int64_t)(ring_bytes / 4 / 16);
+    if (hipHostMalloc((void**)&s->ring_mem, (size_t)n_rows * 12 + (size_t)n_lps * 16, hipHostMallocDefault) !=
+        hipSuccess) {
+        s->ring_mem = nullptr;
+        rgb_server_destroy(s);
+        return RGB_ERR_OOM;
+    }
+    s->r_end = reinterpret_cast<int64_t*>(s->ring_mem);
+    s->r_cx = reinterpret_cast<float*>(s->r_end + n_lps);
+    s->r_cy = s->r_cx + n_lps;
+    s->r_ax = s->r_cy + n_lps;
+    s->r_ay = s->r_ax + n_rows;
+    s->r_b = s->r_ay + n_rows;
+    s->rows = rgb::Ring(n_rows);
+    s->lps = rgb::Ring(n_lps);
     s->slots.resize((size_t)o.n_streams);
+    const size_t cap = (size_t)o.max_batch_lps;
     for (auto& sl : s->slots) {
+        sl.out_at = Layout::al(8 * (cap + 1));
         if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
-            hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess) {
+            hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess ||
+            hipHostMalloc((void**)&sl.pinned, sl.out_at + 3 * Layout::al(4 * cap), hipHostMallocDefault) !=
+                hipSuccess) {
+            sl.pinned = nullptr;
             rgb_server_destroy(s);
             return RGB_ERR_DEVICE;
         }
@@ -310,7 +353,8 @@ rgb_err_t rgb_server_submit(rgb_server_t* srv, int64_t num_lps, int64_t num_cons
     if (num_lps > 0 && (!cx || !cy)) return RGB_ERR_INVALID_ARG;
     if (num_constraints > 0 && (!ax || !ay || !b)) return RGB_ERR_INVALID_ARG;
     auto t0 = Clock::now();
-    if (num_lps > srv->opts.max_batch_lps ||
+    if (num_lps > srv->opts.max_batch_lps || num_constraints > srv->rows.capacity() ||
+        num_lps > srv->lps.capacity() ||
         srv->arena.rounded(Layout(num_lps, num_constraints).total) > srv->arena.capacity()) {
         std::lock_guard<std::mutex> lk(srv->mu);
         srv->stats.rejected_too_large++;
@@ -324,28 +368,45 @@ rgb_err_t rgb_server_submit(rgb_server_t* srv, int64_t num_lps, int64_t num_cons
     auto r = std::make_unique<Request>();
     r->B = num_lps;
     r->N = num_constraints;
-    r->offsets.assign(offsets, offsets + num_lps + 1);
-    r->ax.assign(ax, ax + num_constraints);
-    r->ay.assign(ay, ay + num_constraints);
-    r->b.assign(b, b + num_constraints);
-    r->cx.assign(cx, cx + num_lps);
-    r->cy.assign(cy, cy + num_lps);
     r->x.resize((size_t)num_lps);
     r->y.resize((size_t)num_lps);
     r->st.resize((size_t)num_lps);
     r->t_submit = t0;
+    Request* q = r.get();
     {
         std::lock_guard<std::mutex> lk(srv->mu);
-        if ((int64_t)srv->queue.size() >= srv->opts.max_pending) {
+        bool room = (int64_t)srv->queue.size() < srv->opts.max_pending;
+        if (room && !srv->lps.alloc(num_lps, q->lp_pos, q->lp_blk)) room = false;
+        if (room && !srv->rows.alloc(num_constraints, q->row_pos, q->row_blk)) {
+            srv->lps.release(q->lp_blk);
+            room = false;
+        }
+        if (!room) {
             srv->stats.rejected_busy++;
             return RGB_ERR_BUSY;
         }
-        r->id = srv->next_id++;
-        *ticket = r->id;
-        srv->queue.push_back(r.get());
-        srv->reqs[r->id] = std::move(r);
+        q->id = srv->next_id++;
+        *ticket = q->id;
+        srv->queue.push_back(q);  // not ready yet: the scheduler stops in front of it
+        srv->reqs[q->id] = std::move(r);
         srv->stats.submitted++;
         srv->stats.pending = (int32_t)srv->queue.size();
+    }
+    // the one copy of the request, outside the lock, into its ring blocks
+    if (num_lps > 0) {
+        int64_t* e = srv->r_end + q->lp_pos;
+        for (int64_t k = 0; k < num_lps; ++k) e[k] = offsets[k + 1];
+        std::memcpy(srv->r_cx + q->lp_pos, cx, 4 * (size_t)num_lps);
+        std::memcpy(srv->r_cy + q->lp_pos, cy, 4 * (size_t)num_lps);
+    }
+    if (num_constraints > 0) {
+        std::memcpy(srv->r_ax + q->row_pos, ax, 4 * (size_t)num_constraints);
+        std::memcpy(srv->r_ay + q->row_pos, ay, 4 * (size_t)num_constraints);
+        std::memcpy(srv->r_b + q->row_pos, b, 4 * (size_t)num_constraints);
+    }
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        q->ready = true;
     }
     srv->cv_work.notify_one();
     return RGB_OK;
@@ -412,6 +473,7 @@ rgb_err_t rgb_server_destroy(rgb_server_t* srv) {
         if (sl.stream) (void)hipStreamDestroy(sl.stream);
         if (sl.pinned) (void)hipHostFree(sl.pinned);
     }
+    if (srv->ring_mem) (void)hipHostFree(srv->ring_mem);
     if (srv->arena_mem) (void)hipFree(srv->arena_mem);
     if (srv->ctx) rgb_ctx_destroy(srv->ctx);
     delete srv;

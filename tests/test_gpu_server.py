@@ -70,14 +70,19 @@ def test_alone_vs_mix(rgb, oracle_lib):
 
 
 def test_budget_and_backpressure(rgb):
-    srv = rgb.Server(n_streams=1, max_batch_lps=300, hbm_budget=1 << 20, max_pending=4)
+    # one stream, the plain kernel: a request of four 16,384-row LPs keeps the
+    # stream busy for milliseconds (each LP is one lane's serial work), so the
+    # small requests behind it pile up past max_pending
+    srv = rgb.Server(n_streams=1, max_batch_lps=300, hbm_budget=1 << 20, max_pending=4, variant="plain")
     big = gen.uniform_batch(500, 64, seed=3)
     with pytest.raises(rgb.RequestTooLarge):
         srv.submit(big)  # more LPs than a micro-batch may hold
     wide = gen.uniform_batch(200, 600, seed=3)
     with pytest.raises(rgb.RequestTooLarge):
         srv.submit(wide)  # more bytes than the arena
-    small = gen.uniform_batch(250, 256, seed=4)
+    slow = gen.uniform_batch(4, 16384, seed=5)
+    small = gen.uniform_batch(250, 64, seed=4)
+    t_slow = srv.submit(slow)
     tickets, busy = [], 0
     for _ in range(40):
         try:
@@ -86,6 +91,7 @@ def test_budget_and_backpressure(rgb):
             busy += 1
     _say(f"[gpu] accepted {len(tickets)}, busy {busy}")
     assert busy > 0 and len(tickets) >= 4
+    srv.wait(t_slow)
     first = None
     for t in tickets:
         x, y, st, lat = srv.wait(t)
@@ -111,4 +117,37 @@ def test_empty_and_invalid_requests(rgb):
     bad.offsets[2] = bad.offsets[1] - 1  # decreasing
     with pytest.raises(rgb.RgbError):
         srv.submit(bad)
+    srv.close()
+
+
+def test_host_ring_full_and_wrap(rgb, oracle_lib):
+    """A 1 MiB host ring (65,536 rows) holds two to four of these requests:
+    submissions see BUSY until earlier ones finish, the ring wraps several
+    times, and every result is still right and equal across repeats."""
+    srv = rgb.Server(n_streams=2, max_batch_lps=2000, hbm_budget=64 << 20, host_ring_mib=1)
+    reqs = [gen.uniform_batch(60 + 7 * i, 256, seed=40 + i) for i in range(12)]
+    refs = [oracle_lib.solve(r) for r in reqs]
+    busy, tickets = 0, []
+    for rep in range(3):
+        _say(f"[gpu] ring pass {rep}")
+        for i, r in enumerate(reqs):
+            while True:
+                try:
+                    tickets.append((srv.submit(r), i))
+                    break
+                except rgb.ServerBusy:
+                    busy += 1
+                    time.sleep(0.0005)
+    first = {}
+    for t, i in tickets:
+        x, y, st, _ = srv.wait(t)
+        bs, bx = lpcheck.compare(st, x, y, refs[i]["status"], refs[i]["x"], refs[i]["y"])
+        assert len(bs) == 0 and len(bx) == 0
+        if i in first:
+            assert np.array_equal(st, first[i][2]) and np.array_equal(x, first[i][0], equal_nan=True)
+        else:
+            first[i] = (x, y, st)
+    stats = srv.stats()
+    _say(f"[gpu] busy {busy}, stats {stats}")
+    assert busy > 0 and stats["completed"] == len(tickets) and stats["arena_bytes_in_use"] == 0
     srv.close()

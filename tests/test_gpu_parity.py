@@ -171,6 +171,24 @@ def test_sizes_around_group_widths(rgb, oracle_lib, m):
         _check(bt, ref, _run(rgb, bt, variant, g, s), f"overflow{m}/{variant}/{g}x{s}")
 
 
+def test_one_huge_lp(rgb, oracle_lib):
+    """One LP of 2^20 rows between small ones: the largest size class, the
+    longest 1D LPs (a pooled round then serves one LP with most of the wave)."""
+    bt = gen.concat([gen.uniform_batch(3, 40, seed=6), gen.uniform_batch(1, 1 << 20, seed=7),
+                     gen.uniform_batch(5, 300, seed=8)])
+    ref = oracle_lib.solve(bt)
+    base = None
+    for variant, g, s in (("plain", 0, 0), ("batched", 64, 0), ("batched", 8, 0), ("persistent", 0, 0),
+                          ("binned", 0, 0), ("pooled", 4, -1), ("pooled", 16, 0)):
+        _say(f"[gpu] case=huge variant={variant} G={g} S={s}")
+        got = _run(rgb, bt, variant, g, s, n1d=True)
+        _check(bt, ref, got, f"huge/{variant}/{g}")
+        if base is None:
+            base = got
+        for a, b_ in zip(got, base):
+            assert np.array_equal(a, b_, equal_nan=True)
+
+
 @pytest.mark.parametrize("variant", ["persistent", "pooled"])
 @pytest.mark.parametrize("name", ["uniform", "uneven", "crowd"])
 def test_full_size_sampled(rgb, oracle_lib, name, variant):

@@ -249,6 +249,26 @@ rgb_err_t rgb_server_stats(rgb_server_t* srv, rgb_server_stats_t* out);
  * everything; requests not yet admitted are dropped.  NULL is a no-op. */
 rgb_err_t rgb_server_destroy(rgb_server_t* srv);
 
+/* ---------------------------------------------------------------------------
+ * Reduction microbenchmark (the bound-combining step of Sec. 3).
+ *
+ * rgb_reduce_bench_run computes out[s] = min(in[s c .. s c + c - 1]) for every
+ * segment s of `contention` = c consecutive values, with one of four
+ * methods, so their cost can be compared as c grows (c = how many work units
+ * meet in one bound).  in: device float[n], out: device float[n / c]; c a
+ * power of two in [2, 4096], n a multiple of c.  Enqueued on `stream`;
+ * results are the exact minima for every method.  Errors: INVALID_ARG, DEVICE.
+ * ------------------------------------------------------------------------- */
+typedef enum {
+    RGB_REDUCE_LDS_ATOMIC = 0,    /* LDS min per value, the paper's shared-memory atomics */
+    RGB_REDUCE_GLOBAL_ATOMIC = 1, /* device-memory min per value */
+    RGB_REDUCE_DPP = 2,           /* DPP butterfly in the wave, LDS across the block's waves */
+    RGB_REDUCE_SERIAL = 3         /* one lane per segment */
+} rgb_reduce_method_t;
+
+rgb_err_t rgb_reduce_bench_run(int32_t method, int32_t contention, int64_t n, const float* in, float* out,
+                               void* stream);
+
 #ifdef __cplusplus
 }
 #endif

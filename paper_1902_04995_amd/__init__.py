@@ -129,6 +129,8 @@ def lib():
         L.rgb_server_stats.restype = I32
         L.rgb_server_destroy.argtypes = [P]
         L.rgb_server_destroy.restype = I32
+        L.rgb_reduce_bench_run.argtypes = [I32, I32, I64, P, P, P]
+        L.rgb_reduce_bench_run.restype = I32
         _lib = L
     return _lib
 
@@ -450,3 +452,23 @@ class DeviceBatch:
 
     def plan(self, **kw):
         return Plan(self.offsets, self.ax, self.ay, self.b, self.cx, self.cy, **kw)
+
+
+REDUCE_METHODS = {"lds_atomic": 0, "global_atomic": 1, "dpp": 2, "serial": 3}
+
+
+def reduce_bench_run(method, contention, values, out=None, stream=None):
+    """Segment minima of a device float tensor with one of the reduction
+    methods of rgb_reduce_bench_run (contention = segment length)."""
+    import torch
+    _check_tensor(values, "values", torch.float32, values.device)
+    n = values.numel()
+    if out is None:
+        out = torch.empty(n // int(contention), dtype=torch.float32, device=values.device)
+    if stream is None:
+        stream = torch.cuda.current_stream(values.device)
+    m = REDUCE_METHODS[method] if isinstance(method, str) else int(method)
+    rc = lib().rgb_reduce_bench_run(m, int(contention), n, _ptr(values), _ptr(out), ctypes.c_void_p(stream.cuda_stream))
+    if rc != 0:
+        raise RgbError(f"rgb_reduce_bench_run failed ({rc})")
+    return out

@@ -105,6 +105,40 @@ def served_leg(rgb, gen, n_requests, load, pool_size=96, seed=0):
     return out
 
 
+def host_leg(rgb, bt, tuning, reps=3):
+    """The transfer-inclusive rate: the workload solved from host memory to
+    host memory (rgb_solve_batch_host: chunks through three streams), with
+    pinned and with pageable buffers, and a plain host-to-device copy of the
+    inputs for scale.  Context only: `value` never includes transfers."""
+    import numpy as np
+    import torch
+    kw = {}  # AUTO: the context's (autotuned) configuration, as in the timed steps
+    pin = lambda a: torch.from_numpy(np.ascontiguousarray(a)).pin_memory()
+    args = [pin(bt.offsets)] + [pin(a) for a in (bt.ax, bt.ay, bt.b, bt.cx, bt.cy)]
+    out = (torch.empty(bt.num_lps, dtype=torch.float32).pin_memory(),
+           torch.empty(bt.num_lps, dtype=torch.float32).pin_memory(),
+           torch.empty(bt.num_lps, dtype=torch.int32).pin_memory())
+    res = {}
+    for name, a, o in (("pinned", args, out), ("pageable", [bt.offsets, bt.ax, bt.ay, bt.b, bt.cx, bt.cy], None)):
+        rgb.solve_batch_host(*a, out=o, **kw)  # warm-up: buffers and streams
+        ms = [rgb.solve_batch_host(*a, out=o, **kw)[3] for _ in range(reps)]
+        best = float(np.median(ms))
+        res[name] = {"ms": best, "lps_per_s": bt.num_lps / (best / 1e3)}
+    h2d_bytes = sum(t.numel() * t.element_size() for t in args)
+    dev = torch.empty(h2d_bytes // 4, dtype=torch.float32, device="cuda")
+    flat = torch.empty(h2d_bytes // 4, dtype=torch.float32).pin_memory()
+    dev.copy_(flat, non_blocking=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        dev.copy_(flat, non_blocking=True)
+    torch.cuda.synchronize()
+    h2d_ms = (time.perf_counter() - t0) * 1e3 / reps
+    res["h2d_probe"] = {"bytes": h2d_bytes, "ms": h2d_ms, "gbs": h2d_bytes / (h2d_ms / 1e3) / 1e9}
+    res["configuration"] = (tuning or {}).get("variant", "auto")
+    return res
+
+
 def kernel_name(variant, tuning, lanes=0):
     """The solve kernel a call runs, with the template arguments that tell
     its instances apart (as in the profiler's kernel names)."""
@@ -131,6 +165,7 @@ def main():
     ap.add_argument("--tune-budget-ms", type=float, default=3000.0)
     ap.add_argument("--served-requests", type=int, default=1500, help="0 skips the served leg")
     ap.add_argument("--served-load", type=float, default=0.7)
+    ap.add_argument("--no-host", action="store_true", help="skip the host-to-host (transfer-inclusive) leg")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -216,6 +251,11 @@ def main():
                  "hbm_gbs": alg_bytes / (p_kern / 1e3) / 1e9, "steps": p_steps}
         print(f"[bench] plain: {p_ms:.3f} ms/step", file=sys.stderr, flush=True)
 
+    host = None
+    if not args.no_host:
+        host = host_leg(rgb, bt, tuning)
+        print(f"[bench] host path: {json.dumps(host)}", file=sys.stderr, flush=True)
+
     served = None
     if args.served_requests > 0:
         served = served_leg(rgb, gen, args.served_requests, args.served_load)
@@ -275,6 +315,7 @@ def main():
                      "algorithmic_bytes_per_launch": alg_bytes,
                      "kernel_ms_mean": kern_ms, "kernel_ms_median": kern_med},
         "cpu_baseline": cpu,
+        "host_path": host,
         "served": served,
     }
     print(json.dumps(line))

@@ -249,6 +249,23 @@ rgb_err_t rgb_server_stats(rgb_server_t* srv, rgb_server_stats_t* out);
  * everything; requests not yet admitted are dropped.  NULL is a no-op. */
 rgb_err_t rgb_server_destroy(rgb_server_t* srv);
 
+/* Solve a batch held in HOST memory and return the results to host memory
+ * (the transfer-inclusive path; Sec. 4 counts transfers in its timings).
+ * Blocking.  Arguments as rgb_solve_batch, but every pointer is host memory;
+ * the offsets must be non-decreasing with offsets[0] >= 0 and
+ * offsets[num_lps] <= num_constraints (the batch is cut into chunks of whole
+ * LPs of about `chunk_rows` rows, 0 = 8 Mi rows).  Chunks go through three
+ * streams so that copies overlap solves; buffers allocated with hipHostMalloc
+ * (pinned) are copied by DMA directly, other memory is staged through pinned
+ * buffers with a parallel memcpy.  Results are exactly those of
+ * rgb_solve_batch on the same data.  opts as for rgb_solve_batch except that
+ * n_1dlp_out and the events must be NULL.  *ms_out (may be NULL) receives the
+ * wall time of the call.  Errors: INVALID_ARG, OOM, DEVICE. */
+rgb_err_t rgb_solve_batch_host(rgb_ctx_t* ctx, int64_t num_lps, int64_t num_constraints, const int64_t* offsets,
+                               const float* ax, const float* ay, const float* b, const float* cx, const float* cy,
+                               float* x_out, float* y_out, int32_t* status_out, const rgb_solve_opts_t* opts,
+                               int64_t chunk_rows, double* ms_out);
+
 /* ---------------------------------------------------------------------------
  * Reduction microbenchmark (the bound-combining step of Sec. 3).
  *

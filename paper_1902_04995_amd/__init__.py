@@ -129,6 +129,9 @@ def lib():
         L.rgb_server_stats.restype = I32
         L.rgb_server_destroy.argtypes = [P]
         L.rgb_server_destroy.restype = I32
+        L.rgb_solve_batch_host.argtypes = [P, I64, I64] + [P] * 9 + [ctypes.POINTER(_SolveOpts), I64,
+                                                                       ctypes.POINTER(ctypes.c_double)]
+        L.rgb_solve_batch_host.restype = I32
         L.rgb_reduce_bench_run.argtypes = [I32, I32, I64, P, P, P]
         L.rgb_reduce_bench_run.restype = I32
         _lib = L
@@ -472,3 +475,31 @@ def reduce_bench_run(method, contention, values, out=None, stream=None):
     if rc != 0:
         raise RgbError(f"rgb_reduce_bench_run failed ({rc})")
     return out
+
+
+def solve_batch_host(offsets, ax, ay, b, cx, cy, *, variant="auto", lanes_per_lp=0, pool_wait=0, pool_rows=0,
+                     chunk=0, grid=0, queue_share=0, chunk_rows=0, out=None, ctx: Context | None = None):
+    """Solve a batch in host memory (numpy arrays or CPU tensors; pinned ones
+    are copied by DMA directly) and return (x, y, status, wall_ms) in host
+    memory (rgb_solve_batch_host)."""
+    import numpy as np
+
+    def host(a, dt):
+        if hasattr(a, "numpy"):
+            assert a.device.type == "cpu" and a.is_contiguous()
+            return a
+        return np.ascontiguousarray(a, dtype=dt)
+
+    arrs = [host(offsets, np.int64)] + [host(a, np.float32) for a in (ax, ay, b, cx, cy)]
+    B = (arrs[0].numel() if hasattr(arrs[0], "numel") else arrs[0].shape[0]) - 1
+    N = arrs[1].numel() if hasattr(arrs[1], "numel") else arrs[1].shape[0]
+    if out is None:
+        out = (np.empty(B, np.float32), np.empty(B, np.float32), np.empty(B, np.int32))
+    addr = lambda a: ctypes.c_void_p(a.data_ptr() if hasattr(a, "data_ptr") else a.ctypes.data)
+    ctx = ctx or context(0)
+    opts = make_opts(variant, lanes_per_lp, pool_wait, chunk, grid, None, None, queue_share, pool_rows)
+    ms = ctypes.c_double()
+    rc = lib().rgb_solve_batch_host(ctx.handle, B, N, *[addr(a) for a in arrs], *[addr(a) for a in out],
+                                    ctypes.byref(opts), int(chunk_rows), ctypes.byref(ms))
+    ctx.check(rc, "rgb_solve_batch_host")
+    return out[0], out[1], out[2], ms.value

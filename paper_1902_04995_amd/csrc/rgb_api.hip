@@ -35,6 +35,7 @@ struct rgb_ctx {
     int persist_blocks_per_cu = 1;
     rgb_tuning_t tuning{};
     std::vector<WsSlot> slots;
+    rgb::HostPath* host = nullptr;  // rgb_solve_batch_host state, made on first use
     std::string last_error;
 };
 
@@ -265,6 +266,7 @@ rgb_err_t enqueue(rgb_ctx_t* ctx, const rgb::Problem& P, int variant, const rgb_
 }  // namespace
 
 int rgb::ctx_device(const rgb_ctx* ctx) { return ctx->device; }
+rgb::HostPath*& rgb::ctx_host_path(rgb_ctx* ctx) { return ctx->host; }
 
 extern "C" {
 
@@ -296,6 +298,7 @@ rgb_err_t rgb_ctx_destroy(rgb_ctx_t* ctx) {
     if (!ctx) return RGB_OK;
     {
         DeviceGuard guard(ctx->device);
+        rgb::destroy_host_path(ctx->host);
         for (auto& s : ctx->slots)
             if (s.mem) (void)hipFree(s.mem);
     }

@@ -49,6 +49,12 @@ struct PersistPlan {
 // Device of a context (for the server, which only sees the opaque type).
 int ctx_device(const struct ::rgb_ctx* ctx);
 
+// State of rgb_solve_batch_host (streams, device and pinned chunk buffers),
+// kept in the context and freed with it.
+struct HostPath;
+HostPath*& ctx_host_path(struct ::rgb_ctx* ctx);
+void destroy_host_path(HostPath* h);
+
 hipError_t launch_persistent(const Problem& P, const Workspace& W, const PersistPlan& plan, int grid, bool binned,
                              hipStream_t stream, hipEvent_t ev_begin, hipEvent_t ev_end);
 int persist_blocks_per_cu();

@@ -267,6 +267,59 @@ rgb_err_t rgb_solve_batch_host(rgb_ctx_t* ctx, int64_t num_lps, int64_t num_cons
                                int64_t chunk_rows, double* ms_out);
 
 /* ---------------------------------------------------------------------------
+ * Crowd time step on the device (the collision-avoidance use that motivates
+ * the paper, Sec. 1 and 5): every agent's velocity is the optimum of a 2D LP
+ * built from its neighbours.
+ *
+ * rgb_crowd_step, on `stream`, for agents at (px, py) with preferred
+ * velocities (gx, gy):
+ *   1. bins the agents into square cells of side `cell` over `bounds`;
+ *   2. for agent i finds its k_i nearest other agents, exactly, ordered by
+ *      the FP32 squared distance (dx*dx + dy*dy) and then by index;
+ *   3. writes LP i: for each neighbour j, the half-plane n.v <= (d - radius)/2
+ *      with n the unit vector from i towards j and d their distance (n =
+ *      (1, 0) when d = 0), then the speed disc |v| <= vmax as n_disc tangent
+ *      half-planes (normals at angles 2 pi q / n_disc), all rows ordered by
+ *      SplitMix64 keys: row t of agent i at step s gets key
+ *      splitmix64_nth(seed, (s << 40) + (i << 8) + t + 1), rows are sorted by
+ *      the key's bits 7..63, then by t;
+ *   4. solves the LPs (rgb_solve_batch, objective (gx, gy)), writing x* to
+ *      (vx, vy) and the status to `status`;
+ *   5. sets v = 0 where the LP is not OPTIMAL, moves p += dt v and clamps p
+ *      to `bounds`.
+ * px, py, gx, gy, vx, vy, status: device arrays of n_agents.  Positions must
+ * lie inside `bounds` (the kNN search relies on it; step 5 keeps them there).
+ * `step` (0 .. 2^23 - 1) feeds the row-order keys; opts as for
+ * rgb_solve_batch without n_1dlp_out or events.  Errors: INVALID_ARG, DEVICE.
+ * ------------------------------------------------------------------------- */
+typedef struct rgb_crowd rgb_crowd_t;
+
+typedef struct {
+    float radius;    /* 0 = 0.3 */
+    float vmax;      /* 0 = 1 */
+    float dt;        /* 0 = 0.1 */
+    float cell;      /* grid cell side; 0 = 2 */
+    int32_t n_disc;  /* speed-disc rows, 3..63; 0 = 16 */
+    int32_t reserved;
+    uint64_t seed;   /* row-order keys */
+} rgb_crowd_opts_t;
+
+/* n_agents >= 2; k: HOST int32[n_agents], neighbours per agent, 1..64 and
+ * below n_agents; bounds: HOST float[4] = {x0, y0, x1, y1}.  Allocates the
+ * device buffers of the step (rows, grid) on ctx's device; ctx must outlive
+ * the crowd.  Errors: INVALID_ARG, OOM, DEVICE. */
+rgb_err_t rgb_crowd_create(rgb_ctx_t* ctx, int64_t n_agents, const int32_t* k, const float bounds[4],
+                           const rgb_crowd_opts_t* opts, rgb_crowd_t** out);
+rgb_err_t rgb_crowd_step(rgb_crowd_t* crowd, float* px, float* py, const float* gx, const float* gy, float* vx,
+                         float* vy, int32_t* status, int64_t step, const rgb_solve_opts_t* opts, void* stream);
+/* Total rows of the crowd's LPs (sum of k_i + n_disc). */
+rgb_err_t rgb_crowd_num_rows(const rgb_crowd_t* crowd, int64_t* num_constraints);
+/* Copy the LPs built by the last step into DEVICE buffers (offsets:
+ * n_agents + 1, rows: rgb_crowd_num_rows), enqueued on `stream`. */
+rgb_err_t rgb_crowd_rows(const rgb_crowd_t* crowd, int64_t* offsets, float* ax, float* ay, float* b, void* stream);
+rgb_err_t rgb_crowd_destroy(rgb_crowd_t* crowd);
+
+/* ---------------------------------------------------------------------------
  * Reduction microbenchmark (the bound-combining step of Sec. 3).
  *
  * rgb_reduce_bench_run computes out[s] = min(in[s c .. s c + c - 1]) for every

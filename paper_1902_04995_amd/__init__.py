@@ -71,6 +71,11 @@ class Tuning(ctypes.Structure):
         return t
 
 
+class _CrowdOpts(ctypes.Structure):
+    _fields_ = [("radius", ctypes.c_float), ("vmax", ctypes.c_float), ("dt", ctypes.c_float), ("cell", ctypes.c_float),
+                ("n_disc", ctypes.c_int32), ("reserved", ctypes.c_int32), ("seed", ctypes.c_uint64)]
+
+
 class _ServerOpts(ctypes.Structure):
     _fields_ = [("hbm_budget", ctypes.c_uint64), ("n_streams", ctypes.c_int32), ("max_batch_lps", ctypes.c_int32),
                 ("max_pending", ctypes.c_int32), ("variant", ctypes.c_int32), ("one_request_per_batch", ctypes.c_int32),
@@ -132,6 +137,16 @@ def lib():
         L.rgb_solve_batch_host.argtypes = [P, I64, I64] + [P] * 9 + [ctypes.POINTER(_SolveOpts), I64,
                                                                        ctypes.POINTER(ctypes.c_double)]
         L.rgb_solve_batch_host.restype = I32
+        L.rgb_crowd_create.argtypes = [P, I64, P, P, ctypes.POINTER(_CrowdOpts), ctypes.POINTER(P)]
+        L.rgb_crowd_create.restype = I32
+        L.rgb_crowd_step.argtypes = [P] + [P] * 7 + [I64, ctypes.POINTER(_SolveOpts), P]
+        L.rgb_crowd_step.restype = I32
+        L.rgb_crowd_num_rows.argtypes = [P, ctypes.POINTER(ctypes.c_int64)]
+        L.rgb_crowd_num_rows.restype = I32
+        L.rgb_crowd_rows.argtypes = [P, P, P, P, P, P]
+        L.rgb_crowd_rows.restype = I32
+        L.rgb_crowd_destroy.argtypes = [P]
+        L.rgb_crowd_destroy.restype = I32
         L.rgb_reduce_bench_run.argtypes = [I32, I32, I64, P, P, P]
         L.rgb_reduce_bench_run.restype = I32
         _lib = L
@@ -503,3 +518,69 @@ def solve_batch_host(offsets, ax, ay, b, cx, cy, *, variant="auto", lanes_per_lp
                                     ctypes.byref(opts), int(chunk_rows), ctypes.byref(ms))
     ctx.check(rc, "rgb_solve_batch_host")
     return out[0], out[1], out[2], ms.value
+
+
+class Crowd:
+    """Crowd time step on the device (rgb_crowd_*): kNN, the agents' LPs,
+    the batched solve and the position update, all on one stream."""
+
+    def __init__(self, k, bounds, *, radius=0.3, vmax=1.0, dt=0.1, cell=2.0, n_disc=16, seed=0,
+                 ctx: Context | None = None):
+        import numpy as np
+        self.ctx = ctx or context(0)
+        self.k = np.ascontiguousarray(k, dtype=np.int32)
+        self.n = int(self.k.shape[0])
+        b = np.ascontiguousarray(bounds, dtype=np.float32)
+        o = _CrowdOpts()
+        o.radius, o.vmax, o.dt, o.cell, o.n_disc, o.seed = radius, vmax, dt, cell, int(n_disc), int(seed)
+        self.opts = o
+        h = ctypes.c_void_p()
+        rc = lib().rgb_crowd_create(self.ctx.handle, self.n, ctypes.c_void_p(self.k.ctypes.data),
+                                    ctypes.c_void_p(b.ctypes.data), ctypes.byref(o), ctypes.byref(h))
+        if rc != 0:
+            raise RgbError(f"rgb_crowd_create failed ({rc})")
+        self.handle = h
+        r = ctypes.c_int64()
+        lib().rgb_crowd_num_rows(self.handle, ctypes.byref(r))
+        self.num_rows = r.value
+
+    def step(self, px, py, gx, gy, vx, vy, status, step, stream=None, **solve_kw):
+        """One time step; px, py are updated in place, (vx, vy, status) get
+        the chosen velocities and the LP statuses (CUDA tensors)."""
+        import torch
+        for t, dt in ((px, torch.float32), (py, torch.float32), (gx, torch.float32), (gy, torch.float32),
+                      (vx, torch.float32), (vy, torch.float32), (status, torch.int32)):
+            _check_tensor(t, "crowd array", dt, px.device)
+            if t.numel() != self.n:
+                raise ValueError("crowd arrays must hold one entry per agent")
+        if stream is None:
+            stream = torch.cuda.current_stream(px.device)
+        opts = make_opts(**solve_kw)
+        rc = lib().rgb_crowd_step(self.handle, *[_ptr(t) for t in (px, py, gx, gy, vx, vy, status)], int(step),
+                                  ctypes.byref(opts), ctypes.c_void_p(stream.cuda_stream))
+        self.ctx.check(rc, "rgb_crowd_step")
+
+    def rows(self, stream=None):
+        """The LPs of the last step as CUDA tensors (offsets, ax, ay, b)."""
+        import torch
+        dev = torch.device("cuda", self.ctx.device)
+        offs = torch.empty(self.n + 1, dtype=torch.int64, device=dev)
+        ax, ay, b = (torch.empty(self.num_rows, dtype=torch.float32, device=dev) for _ in range(3))
+        if stream is None:
+            stream = torch.cuda.current_stream(dev)
+        rc = lib().rgb_crowd_rows(self.handle, _ptr(offs), _ptr(ax), _ptr(ay), _ptr(b),
+                                  ctypes.c_void_p(stream.cuda_stream))
+        if rc != 0:
+            raise RgbError(f"rgb_crowd_rows failed ({rc})")
+        return offs, ax, ay, b
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().rgb_crowd_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

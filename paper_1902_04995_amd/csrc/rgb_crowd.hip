@@ -1,0 +1,439 @@
+// Crowd time step kept on the device: the collision-avoidance use of batched
+// 2D LPs that motivates the paper (each agent picks its velocity by an LP
+// over half-planes from its neighbours).  One step, all on one stream:
+//
+//   grid      agents binned into square cells (count, scan, scatter);
+//   build     one wave per agent: its k nearest other agents (exact, ordered
+//             by FP32 squared distance, then index), one half-plane per
+//             neighbour (unit normal towards it, offset half the distance
+//             minus the radius), the speed disc |v| <= vmax as tangent
+//             half-planes, all rows put in a random order (Seidel's method
+//             wants one) given by SplitMix64 keys, written as the agent's LP;
+//   solve     rgb_solve_batch with the preferred velocities as objectives;
+//   integrate v = x* (0 for an infeasible LP), p += dt v, clamped to the room.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/rgb.h"
+#include "rgb_internal.hpp"
+
+namespace {
+
+constexpr int kMaxK = 64;      // neighbours per agent at most
+constexpr int kMaxDisc = 63;   // speed-disc rows at most (k + disc <= 127)
+constexpr int kCand = 256;     // candidate keys held per agent while searching
+constexpr int kSlots = 128;    // row slots per agent
+constexpr int kWaves = 4;      // agents per block
+constexpr uint64_t kNone = ~0ull;
+
+struct Grid {
+    float x0, y0, x1, y1, h, inv_h;
+    float fuzz;  // how far a rounded cell assignment can put a point outside its cell
+    int W, H;
+};
+
+__device__ __forceinline__ int cell_of(float v, float v0, float inv_h, int n) {
+    int c = (int)floorf((v - v0) * inv_h);
+    return c < 0 ? 0 : (c >= n ? n - 1 : c);
+}
+
+__global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ void k_grid_count(const float* px, const float* py, int64_t n, Grid g, int32_t* cell, int32_t* count) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int c = cell_of(py[i], g.y0, g.inv_h, g.H) * g.W + cell_of(px[i], g.x0, g.inv_h, g.W);
+    cell[i] = c;
+    atomicAdd(&count[c], 1);
+}
+
+// Exclusive scan of count[0 .. C) into start[0 .. C] and cursor[0 .. C), one
+// block of 1024 threads, each over a contiguous run of cells.
+__global__ __launch_bounds__(1024) void k_grid_scan(const int32_t* count, int64_t C, int32_t* start,
+                                                    int32_t* cursor) {
+    __shared__ int32_t part[1024];
+    const int t = threadIdx.x;
+    const int64_t per = (C + 1023) / 1024;
+    const int64_t lo = t * per, hi = lo + per < C ? lo + per : C;
+    int32_t sum = 0;
+    for (int64_t c = lo; c < hi; ++c) sum += count[c];
+    part[t] = sum;
+    __syncthreads();
+    for (int d = 1; d < 1024; d <<= 1) {
+        int32_t v = t >= d ? part[t - d] : 0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    int32_t run = part[t] - sum;
+    for (int64_t c = lo; c < hi; ++c) {
+        start[c] = run;
+        cursor[c] = run;
+        run += count[c];
+    }
+    if (t == 1023) start[C] = part[1023];
+}
+
+__global__ void k_grid_scatter(const int32_t* cell, int64_t n, int32_t* cursor, int32_t* sorted) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int pos = atomicAdd(&cursor[cell[i]], 1);
+    sorted[pos] = (int32_t)i;
+}
+
+// SplitMix64 (Steele, Lea and Flood 2014; constants as published by Vigna):
+// the n-th output (n >= 1) of the generator seeded with s is mix(s + n G).
+__device__ __forceinline__ uint64_t splitmix_nth(uint64_t seed, uint64_t n) {
+    uint64_t z = seed + 0x9e3779b97f4a7c15ull * n;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+// Sort the first `len` (a power of two, <= 256) keys of a wave's LDS array,
+// ascending.  Bitonic network; a wave runs in lock step and LDS executes its
+// accesses in order, so no barrier is needed between stages.
+__device__ __forceinline__ void wave_sort(uint64_t* s, int len) {
+    const int lane = __lane_id();
+    for (int k = 2; k <= len; k <<= 1)
+        for (int j = k >> 1; j > 0; j >>= 1)
+            for (int p = lane; p < (len >> 1); p += 64) {
+                const int a = (p / j) * 2 * j + (p % j), b = a + j;
+                const uint64_t x = s[a], y = s[b];
+                if ((x > y) == ((a & k) == 0)) {
+                    s[a] = y;
+                    s[b] = x;
+                }
+                __atomic_signal_fence(__ATOMIC_SEQ_CST);
+            }
+}
+
+__device__ __forceinline__ int pow2_ceil(int n) {
+    int p = 2;
+    while (p < n) p <<= 1;
+    return p;
+}
+
+// Keep the `keep` smallest of the first n keys (sorted, at the front).
+__device__ __forceinline__ int keep_best(uint64_t* s, int n, int keep) {
+    const int len = pow2_ceil(n);
+    for (int t = n + __lane_id(); t < len; t += 64) s[t] = kNone;
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    wave_sort(s, len);
+    return n < keep ? n : keep;
+}
+
+__global__ __launch_bounds__(64 * kWaves) void k_crowd_build(const float* px, const float* py, const int32_t* kk,
+                                                             const int64_t* offsets, int64_t n, Grid g,
+                                                             const int32_t* start, const int32_t* sorted,
+                                                             const float* disc, int n_disc, float radius,
+                                                             uint64_t seed, int64_t step, float* ax, float* ay,
+                                                             float* bb) {
+    __shared__ uint64_t cand_all[kWaves][kCand];
+    __shared__ uint64_t key_all[kWaves][kSlots];
+    __shared__ float row_all[kWaves][3][kSlots];
+    const int w = threadIdx.x >> 6;
+    const int lane = __lane_id();
+    const int64_t i = (int64_t)blockIdx.x * kWaves + w;
+    if (i >= n) return;  // the whole wave
+    uint64_t* cand = cand_all[w];
+    const float pxi = px[i], pyi = py[i];
+    const int ki = kk[i];
+    const int cx = cell_of(pxi, g.x0, g.inv_h, g.W), cy = cell_of(pyi, g.y0, g.inv_h, g.H);
+    const int rmax = max(max(cx, g.W - 1 - cx), max(cy, g.H - 1 - cy));
+
+    // k nearest: rings of cells at Chebyshev distance r, nearest ring first.
+    // Agents beyond ring r are at least r h away, so the search ends once the
+    // k-th best squared distance is clearly below (r h)^2.
+    int nc = 0;
+    for (int r = 0; r <= rmax; ++r) {
+        const int side = r == 0 ? 1 : 8 * r;  // cells in ring r
+        for (int q = 0; q < side; ++q) {
+            int dx, dy;
+            if (r == 0) {
+                dx = dy = 0;
+            } else if (q < 2 * r + 1) {  // bottom row
+                dx = q - r;
+                dy = -r;
+            } else if (q < 4 * r + 2) {  // top row
+                dx = q - (2 * r + 1) - r;
+                dy = r;
+            } else if (q < 6 * r + 1) {  // left column without corners
+                dx = -r;
+                dy = q - (4 * r + 2) - r + 1;
+            } else {  // right column without corners
+                dx = r;
+                dy = q - (6 * r + 1) - r + 1;
+            }
+            const int X = cx + dx, Y = cy + dy;
+            if (X < 0 || X >= g.W || Y < 0 || Y >= g.H) continue;
+            const int c = Y * g.W + X;
+            const int s = start[c], e = start[c + 1];
+            for (int base = s; base < e; base += 64) {
+                const int t = base + lane;
+                int j = t < e ? sorted[t] : -1;
+                bool v = j >= 0 && j != (int)i;
+                uint64_t key = kNone;
+                if (v) {
+                    const float ddx = px[j] - pxi, ddy = py[j] - pyi;
+                    const float d2 = ddx * ddx + ddy * ddy;
+                    key = ((uint64_t)__builtin_bit_cast(uint32_t, d2) << 32) | (uint32_t)j;
+                }
+                const uint64_t bal = __ballot(v);
+                const int cnt = __popcll(bal);
+                if (nc + cnt > kCand) nc = keep_best(cand, nc, ki);
+                const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
+                                                           __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0));
+                if (v) cand[nc + rank] = key;
+                __atomic_signal_fence(__ATOMIC_SEQ_CST);
+                nc += cnt;
+            }
+        }
+        if (r > 0 && nc >= ki) {
+            nc = keep_best(cand, nc, ki);
+            const float dk2 = __builtin_bit_cast(float, (uint32_t)(cand[ki - 1] >> 32));
+            const float lim = (float)r * g.h - 2.0f * g.fuzz;  // unvisited agents are farther than this
+            if (lim > 0.0f && dk2 < lim * lim * 0.999999f) break;
+        }
+    }
+    nc = keep_best(cand, nc, ki);  // sorted; nc == ki (the batch has more than ki agents)
+
+    // rows: neighbours, then the speed disc; keys put them in random order
+    const int m = ki + n_disc;
+    float* rx = row_all[w][0];
+    float* ry = row_all[w][1];
+    float* rb = row_all[w][2];
+    uint64_t* key = key_all[w];
+    for (int t = lane; t < kSlots; t += 64) {
+        uint64_t kt = kNone;
+        if (t < nc) {
+            const int j = (int)(uint32_t)cand[t];
+            const float ddx = px[j] - pxi, ddy = py[j] - pyi;
+            const float dist = sqrtf(ddx * ddx + ddy * ddy);
+            const bool zero = dist == 0.0f;
+            rx[t] = zero ? 1.0f : ddx / dist;
+            ry[t] = zero ? 0.0f : ddy / dist;
+            rb[t] = 0.5f * (dist - radius);
+        } else if (t >= ki && t < m) {
+            rx[t] = disc[2 * (t - ki)];
+            ry[t] = disc[2 * (t - ki) + 1];
+            rb[t] = disc[2 * n_disc];
+        }
+        if (t < m) {
+            const uint64_t ctr = ((uint64_t)step << 40) + ((uint64_t)i << 8) + (uint64_t)t;
+            kt = (splitmix_nth(seed, ctr + 1) & ~uint64_t(127)) | (uint64_t)t;
+        }
+        key[t] = kt;
+    }
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    wave_sort(key, kSlots);
+    const int64_t o = offsets[i];
+    for (int t = lane; t < m; t += 64) {
+        const int src = (int)(key[t] & 127);
+        ax[o + t] = rx[src];
+        ay[o + t] = ry[src];
+        bb[o + t] = rb[src];
+    }
+}
+
+__global__ void k_crowd_integrate(float* px, float* py, float* vx, float* vy, const int32_t* status, int64_t n,
+                                  float dt, Grid g) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float ux = vx[i], uy = vy[i];
+    if (status[i] != 0) ux = uy = 0.0f;  // no feasible velocity: stand still
+    vx[i] = ux;
+    vy[i] = uy;
+    const float sx = dt * ux, sy = dt * uy;
+    float x = px[i] + sx, y = py[i] + sy;
+    x = x < g.x0 ? g.x0 : (x > g.x1 ? g.x1 : x);
+    y = y < g.y0 ? g.y0 : (y > g.y1 ? g.y1 : y);
+    px[i] = x;
+    py[i] = y;
+}
+
+}  // namespace
+
+struct rgb_crowd {
+    rgb_ctx_t* ctx = nullptr;
+    int device = 0;
+    int64_t n = 0, rows = 0, cells = 0;
+    Grid g{};
+    rgb_crowd_opts_t o{};
+    char* mem = nullptr;
+    int32_t* k = nullptr;
+    int64_t* offsets = nullptr;
+    float *ax = nullptr, *ay = nullptr, *b = nullptr, *disc = nullptr;
+    int32_t *cell = nullptr, *count = nullptr, *start = nullptr, *cursor = nullptr, *sorted = nullptr;
+};
+
+extern "C" {
+
+rgb_err_t rgb_crowd_create(rgb_ctx_t* ctx, int64_t n_agents, const int32_t* k, const float bounds[4],
+                           const rgb_crowd_opts_t* opts, rgb_crowd_t** out) {
+    if (!ctx || !k || !bounds || !out || n_agents < 2 || n_agents > (int64_t(1) << 30)) return RGB_ERR_INVALID_ARG;
+    *out = nullptr;
+    rgb_crowd_opts_t o{};
+    if (opts) o = *opts;
+    if (o.radius == 0.0f) o.radius = 0.3f;
+    if (o.vmax == 0.0f) o.vmax = 1.0f;
+    if (o.dt == 0.0f) o.dt = 0.1f;
+    if (o.cell == 0.0f) o.cell = 2.0f;
+    if (o.n_disc == 0) o.n_disc = 16;
+    if (!(o.radius >= 0.0f) || !(o.vmax > 0.0f) || !(o.dt > 0.0f) || !(o.cell > 0.0f) || o.n_disc < 3 ||
+        o.n_disc > kMaxDisc || !std::isfinite(o.radius) || !std::isfinite(o.vmax) || !std::isfinite(o.dt) ||
+        !std::isfinite(o.cell))
+        return RGB_ERR_INVALID_ARG;
+    const float x0 = bounds[0], y0 = bounds[1], x1 = bounds[2], y1 = bounds[3];
+    if (!std::isfinite(x0) || !std::isfinite(y0) || !std::isfinite(x1) || !std::isfinite(y1) || !(x1 > x0) ||
+        !(y1 > y0))
+        return RGB_ERR_INVALID_ARG;
+    const double W = std::ceil((x1 - x0) / (double)o.cell), H = std::ceil((y1 - y0) / (double)o.cell);
+    if (W * H > double(int64_t(1) << 26)) return RGB_ERR_INVALID_ARG;
+    std::vector<int64_t> offs((size_t)n_agents + 1);
+    offs[0] = 0;
+    for (int64_t a = 0; a < n_agents; ++a) {
+        if (k[a] < 1 || k[a] > kMaxK || k[a] > n_agents - 1) return RGB_ERR_INVALID_ARG;
+        offs[a + 1] = offs[a] + k[a] + o.n_disc;
+    }
+    auto* c = new (std::nothrow) rgb_crowd();
+    if (!c) return RGB_ERR_OOM;
+    c->ctx = ctx;
+    c->device = rgb::ctx_device(ctx);
+    c->n = n_agents;
+    c->rows = offs[(size_t)n_agents];
+    c->o = o;
+    c->g.x0 = x0;
+    c->g.y0 = y0;
+    c->g.x1 = x1;
+    c->g.y1 = y1;
+    c->g.h = o.cell;
+    c->g.inv_h = 1.0f / o.cell;
+    c->g.fuzz = (float)(4.0 * std::ldexp(1.0, -23) *
+                        (std::max(std::max(std::fabs(x0), std::fabs(x1)), std::max(std::fabs(y0), std::fabs(y1))) +
+                         o.cell));
+    c->g.W = (int)std::max(1.0, W);
+    c->g.H = (int)std::max(1.0, H);
+    c->cells = (int64_t)c->g.W * c->g.H;
+    // one allocation: k, offsets, rows, disc constants, grid arrays
+    auto al = [](size_t v) { return (v + 255) & ~size_t(255); };
+    const size_t n_ = (size_t)n_agents, R = (size_t)c->rows, C = (size_t)c->cells;
+    const size_t sz_k = al(4 * n_), sz_off = al(8 * (n_ + 1)), sz_row = al(4 * R), sz_disc = al(4 * (2 * kMaxDisc + 1)),
+                 sz_cell = al(4 * n_), sz_cnt = al(4 * (C + 1)), sz_sorted = al(4 * n_);
+    const size_t total = sz_k + sz_off + 3 * sz_row + sz_disc + sz_cell + 3 * sz_cnt + sz_sorted;
+    int prev = 0;
+    if (hipGetDevice(&prev) != hipSuccess) {
+        delete c;
+        return RGB_ERR_DEVICE;
+    }
+    if (c->device != prev && hipSetDevice(c->device) != hipSuccess) {
+        delete c;
+        return RGB_ERR_DEVICE;
+    }
+    rgb_err_t rc = RGB_OK;
+    if (hipMalloc((void**)&c->mem, total) != hipSuccess) {
+        c->mem = nullptr;
+        rc = RGB_ERR_OOM;
+    } else {
+        char* p = c->mem;
+        c->k = reinterpret_cast<int32_t*>(p); p += sz_k;
+        c->offsets = reinterpret_cast<int64_t*>(p); p += sz_off;
+        c->ax = reinterpret_cast<float*>(p); p += sz_row;
+        c->ay = reinterpret_cast<float*>(p); p += sz_row;
+        c->b = reinterpret_cast<float*>(p); p += sz_row;
+        c->disc = reinterpret_cast<float*>(p); p += sz_disc;
+        c->cell = reinterpret_cast<int32_t*>(p); p += sz_cell;
+        c->count = reinterpret_cast<int32_t*>(p); p += sz_cnt;
+        c->start = reinterpret_cast<int32_t*>(p); p += sz_cnt;
+        c->cursor = reinterpret_cast<int32_t*>(p); p += sz_cnt;
+        c->sorted = reinterpret_cast<int32_t*>(p);
+        // the disc: unit normals at angles 2 pi q / n_disc, offset vmax
+        std::vector<float> disc(2 * kMaxDisc + 1, 0.0f);
+        for (int q = 0; q < o.n_disc; ++q) {
+            const double t = 2.0 * M_PI * q / o.n_disc;
+            disc[2 * q] = (float)std::cos(t);
+            disc[2 * q + 1] = (float)std::sin(t);
+        }
+        disc[2 * o.n_disc] = o.vmax;
+        if (hipMemcpy(c->k, k, 4 * n_, hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(c->offsets, offs.data(), 8 * (n_ + 1), hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(c->disc, disc.data(), 4 * disc.size(), hipMemcpyHostToDevice) != hipSuccess)
+            rc = RGB_ERR_DEVICE;
+    }
+    if (c->device != prev) (void)hipSetDevice(prev);
+    if (rc != RGB_OK) {
+        rgb_crowd_destroy(c);
+        return rc;
+    }
+    *out = c;
+    return RGB_OK;
+}
+
+rgb_err_t rgb_crowd_step(rgb_crowd_t* c, float* px, float* py, const float* gx, const float* gy, float* vx, float* vy,
+                         int32_t* status, int64_t step, const rgb_solve_opts_t* opts, void* stream) {
+    if (!c || !px || !py || !gx || !gy || !vx || !vy || !status || step < 0 || step >= (int64_t(1) << 23))
+        return RGB_ERR_INVALID_ARG;
+    if (opts && (opts->n_1dlp_out || opts->ev_begin || opts->ev_end)) return RGB_ERR_INVALID_ARG;
+    int prev = 0;
+    if (hipGetDevice(&prev) != hipSuccess) return RGB_ERR_DEVICE;
+    if (c->device != prev && hipSetDevice(c->device) != hipSuccess) return RGB_ERR_DEVICE;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const int64_t n = c->n, C = c->cells;
+    const unsigned nb = (unsigned)((n + 255) / 256);
+    hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((C + 1 + 255) / 256)), dim3(256), 0, st, c->count, C + 1, 0);
+    hipLaunchKernelGGL(k_grid_count, dim3(nb), dim3(256), 0, st, px, py, n, c->g, c->cell, c->count);
+    hipLaunchKernelGGL(k_grid_scan, dim3(1), dim3(1024), 0, st, c->count, C, c->start, c->cursor);
+    hipLaunchKernelGGL(k_grid_scatter, dim3(nb), dim3(256), 0, st, c->cell, n, c->cursor, c->sorted);
+    hipLaunchKernelGGL(k_crowd_build, dim3((unsigned)((n + kWaves - 1) / kWaves)), dim3(64 * kWaves), 0, st, px, py,
+                       c->k, c->offsets, n, c->g, c->start, c->sorted, c->disc, c->o.n_disc, c->o.radius, c->o.seed,
+                       step, c->ax, c->ay, c->b);
+    rgb_err_t rc = hipGetLastError() == hipSuccess ? RGB_OK : RGB_ERR_DEVICE;
+    if (rc == RGB_OK)
+        rc = rgb_solve_batch(c->ctx, n, c->rows, c->offsets, c->ax, c->ay, c->b, gx, gy, vx, vy, status, opts,
+                             stream);
+    if (rc == RGB_OK) {
+        hipLaunchKernelGGL(k_crowd_integrate, dim3(nb), dim3(256), 0, st, px, py, vx, vy, status, n, c->o.dt, c->g);
+        if (hipGetLastError() != hipSuccess) rc = RGB_ERR_DEVICE;
+    }
+    if (c->device != prev) (void)hipSetDevice(prev);
+    return rc;
+}
+
+rgb_err_t rgb_crowd_num_rows(const rgb_crowd_t* c, int64_t* num_constraints) {
+    if (!c || !num_constraints) return RGB_ERR_INVALID_ARG;
+    *num_constraints = c->rows;
+    return RGB_OK;
+}
+
+rgb_err_t rgb_crowd_rows(const rgb_crowd_t* c, int64_t* offsets, float* ax, float* ay, float* b, void* stream) {
+    if (!c || !offsets || !ax || !ay || !b) return RGB_ERR_INVALID_ARG;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const size_t R = 4 * (size_t)c->rows;
+    bool ok = hipMemcpyAsync(offsets, c->offsets, 8 * (size_t)(c->n + 1), hipMemcpyDeviceToDevice, st) == hipSuccess &&
+              hipMemcpyAsync(ax, c->ax, R, hipMemcpyDeviceToDevice, st) == hipSuccess &&
+              hipMemcpyAsync(ay, c->ay, R, hipMemcpyDeviceToDevice, st) == hipSuccess &&
+              hipMemcpyAsync(b, c->b, R, hipMemcpyDeviceToDevice, st) == hipSuccess;
+    return ok ? RGB_OK : RGB_ERR_DEVICE;
+}
+
+rgb_err_t rgb_crowd_destroy(rgb_crowd_t* c) {
+    if (!c) return RGB_OK;
+    if (c->mem) {
+        int prev = 0;
+        const bool ok = hipGetDevice(&prev) == hipSuccess;
+        if (ok && prev != c->device) (void)hipSetDevice(c->device);
+        (void)hipFree(c->mem);
+        if (ok && prev != c->device) (void)hipSetDevice(prev);
+    }
+    delete c;
+    return RGB_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,115 @@
+"""GPU: the crowd time step on the device (rgb_crowd_*) against its CPU
+reference (oracle/crowd.py) and the LP oracle.
+
+Per step, from the same positions: the LPs the device builds (kNN, rows, row
+order) equal the reference's bit for bit; the LP statuses equal the oracle's
+and the velocities meet the parity bar; the new positions equal an FP32
+integration of the device's velocities bit for bit."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import lpcheck
+from oracle import crowd as cr
+from paper_1902_04995_amd import gen
+
+pytestmark = pytest.mark.gpu
+
+OPTS = dict(radius=0.3, vmax=1.0, dt=0.1, cell=2.0, n_disc=16, seed=77)
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _crowd(n, seed, density):
+    rng = np.random.default_rng(seed)
+    side = math.sqrt(n / density)
+    px = (rng.random(n) * side).astype(np.float32)
+    py = (rng.random(n) * side).astype(np.float32)
+    k = np.minimum(rng.integers(8, 65, n), n - 1).astype(np.int32)
+    ang = rng.random(n) * 2.0 * math.pi
+    return px, py, k, np.cos(ang).astype(np.float32), np.sin(ang).astype(np.float32), (0.0, 0.0, side, side)
+
+
+def _run_steps(oracle_lib, n, seed, density, steps, k_all=None):
+    import torch
+    import paper_1902_04995_amd as rgb
+    px, py, k, gx, gy, bounds = _crowd(n, seed, density)
+    if k_all is not None:
+        k[:] = k_all
+    crowd = rgb.Crowd(k, bounds, **OPTS)
+    t = lambda a: torch.from_numpy(a).cuda()
+    dpx, dpy, dgx, dgy = t(px), t(py), t(gx), t(gy)
+    vx = torch.empty(n, dtype=torch.float32, device="cuda")
+    vy = torch.empty_like(vx)
+    st = torch.empty(n, dtype=torch.int32, device="cuda")
+    seen = np.zeros(4, np.int64)
+    for s in range(steps):
+        p0x, p0y = dpx.cpu().numpy(), dpy.cpu().numpy()
+        _say(f"[gpu] crowd n={n} step {s}")
+        crowd.step(dpx, dpy, dgx, dgy, vx, vy, st, s)
+        torch.cuda.synchronize()
+        offs, ax, ay, b = (a.cpu().numpy() for a in crowd.rows())
+        nbrs = cr.knn(p0x, p0y, k)
+        ref = cr.build_rows(p0x, p0y, k, nbrs, OPTS["radius"], OPTS["vmax"], OPTS["n_disc"], OPTS["seed"], s)
+        assert np.array_equal(offs, ref[0])
+        for got, want, name in zip((ax, ay, b), ref[1:], ("ax", "ay", "b")):
+            bad = np.flatnonzero(got != want)
+            assert bad.size == 0, f"step {s}: {bad.size} rows differ in {name}, first at row {bad[:3]}"
+        status = st.cpu().numpy()
+        ux, uy = vx.cpu().numpy(), vy.cpu().numpy()
+        o = oracle_lib.solve(gen.Batch(offs, ax, ay, b, gx, gy, np.full(n, gen.KIND_CROWD, np.int8)))
+        bs, bx = lpcheck.compare(status, ux, uy, o["status"], o["x"], o["y"])
+        assert len(bs) == 0 and len(bx) == 0, (len(bs), len(bx))
+        seen += np.bincount(status, minlength=4)
+        x1, y1, _, _ = cr.integrate(p0x, p0y, ux, uy, status, OPTS["dt"], bounds)
+        assert np.array_equal(dpx.cpu().numpy(), x1) and np.array_equal(dpy.cpu().numpy(), y1)
+    crowd.close()
+    return seen
+
+
+def test_crowd_steps_match_reference(oracle_lib):
+    seen = _run_steps(oracle_lib, 3000, seed=1, density=4.0, steps=3)
+    _say(f"[gpu] statuses over the steps {seen.tolist()}")
+    assert seen[0] > 0 and seen[1] > 0  # optimal and infeasible (stand-still) agents both occur
+
+
+def test_tiny_crowd_every_agent_a_neighbour(oracle_lib):
+    _run_steps(oracle_lib, 20, seed=2, density=0.05, steps=2, k_all=19)
+
+
+def test_full_size_step_sampled(oracle_lib):
+    """262,144 agents (the crowd workload's size), one step, checked on a
+    sample of agents."""
+    import torch
+    import paper_1902_04995_amd as rgb
+    n = 262144
+    px, py, k, gx, gy, bounds = _crowd(n, seed=3, density=1.0)
+    crowd = rgb.Crowd(k, bounds, **OPTS)
+    t = lambda a: torch.from_numpy(a).cuda()
+    dpx, dpy, dgx, dgy = t(px), t(py), t(gx), t(gy)
+    vx = torch.empty(n, dtype=torch.float32, device="cuda")
+    vy = torch.empty_like(vx)
+    st = torch.empty(n, dtype=torch.int32, device="cuda")
+    _say("[gpu] crowd n=262144 step 0")
+    crowd.step(dpx, dpy, dgx, dgy, vx, vy, st, 0)
+    torch.cuda.synchronize()
+    offs, ax, ay, b = (a.cpu().numpy() for a in crowd.rows())
+    rng = np.random.default_rng(4)
+    sample = np.sort(rng.choice(n, 1500, replace=False))
+    nbrs = cr.knn(px, py, k, agents=sample)
+    for i, nb in zip(sample, nbrs):
+        want = cr.agent_rows(px, py, i, nb, OPTS["radius"], OPTS["vmax"], OPTS["n_disc"], OPTS["seed"], 0)
+        s0, e0 = offs[i], offs[i + 1]
+        for got, w in zip((ax[s0:e0], ay[s0:e0], b[s0:e0]), want):
+            assert np.array_equal(got, w), i
+    sub = gen.Batch(offs, ax, ay, b, gx, gy, np.full(n, gen.KIND_CROWD, np.int8)).subset(sample)
+    o = oracle_lib.solve(sub)
+    status, ux, uy = st.cpu().numpy()[sample], vx.cpu().numpy()[sample], vy.cpu().numpy()[sample]
+    bs, bx = lpcheck.compare(status, ux, uy, o["status"], o["x"], o["y"])
+    assert len(bs) == 0 and len(bx) == 0
+    crowd.close()

@@ -139,6 +139,60 @@ def host_leg(rgb, bt, tuning, reps=3):
     return res
 
 
+def crowd_leg(rgb, n=262144, steps=10, seed=0):
+    """The crowd time step on the device at the crowd workload's size (agents
+    uniform at density 1, k ~ U{8..64} neighbours, 16 speed-disc rows): ms per
+    step eager (explicit step numbers) and as a replayed HIP graph (device step
+    counter), positions reset before each series."""
+    import math
+
+    import numpy as np
+    import torch
+    rng = np.random.default_rng(seed)
+    side = math.sqrt(n)
+    px = (rng.random(n) * side).astype(np.float32)
+    py = (rng.random(n) * side).astype(np.float32)
+    k = rng.integers(8, 65, n).astype(np.int32)
+    ang = rng.random(n) * 2.0 * math.pi
+    g = [torch.from_numpy(a.astype(np.float32)).cuda() for a in (np.cos(ang), np.sin(ang))]
+    crowd = rgb.Crowd(k, (0.0, 0.0, side, side), radius=0.3, vmax=1.0, dt=0.1, cell=2.0, n_disc=16, seed=seed)
+    dpx, dpy = torch.from_numpy(px).cuda(), torch.from_numpy(py).cuda()
+    vx = torch.empty(n, dtype=torch.float32, device="cuda")
+    vy = torch.empty_like(vx)
+    st = torch.empty(n, dtype=torch.int32, device="cuda")
+    side_stream = torch.cuda.Stream()
+    side_stream.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side_stream):
+        for s in range(2):  # warm-up on the stream the graph is captured on
+            crowd.step(dpx, dpy, g[0], g[1], vx, vy, st, s, stream=side_stream)
+    torch.cuda.synchronize()
+
+    def series(fn):
+        dpx.copy_(torch.from_numpy(px))
+        dpy.copy_(torch.from_numpy(py))
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(side_stream)
+        for s in range(steps):
+            fn(s)
+        e1.record(side_stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    eager_ms = series(lambda s: crowd.step(dpx, dpy, g[0], g[1], vx, vy, st, s, stream=side_stream))
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=side_stream):
+        crowd.step(dpx, dpy, g[0], g[1], vx, vy, st, -1, stream=side_stream)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(side_stream):
+        graph_ms = series(lambda s: graph.replay())
+    status = np.bincount(st.cpu().numpy(), minlength=4).tolist()
+    crowd.close()
+    return {"agents": n, "rows_per_step": int(crowd.num_rows), "steps": steps, "eager_ms_per_step": eager_ms,
+            "graph_ms_per_step": graph_ms, "agent_steps_per_s": n / (min(eager_ms, graph_ms) / 1e3),
+            "last_step_status_counts": status}
+
+
 def kernel_name(variant, tuning, lanes=0):
     """The solve kernel a call runs, with the template arguments that tell
     its instances apart (as in the profiler's kernel names)."""
@@ -166,6 +220,7 @@ def main():
     ap.add_argument("--served-requests", type=int, default=1500, help="0 skips the served leg")
     ap.add_argument("--served-load", type=float, default=0.7)
     ap.add_argument("--no-host", action="store_true", help="skip the host-to-host (transfer-inclusive) leg")
+    ap.add_argument("--no-crowd", action="store_true", help="skip the crowd time-step leg")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -256,6 +311,11 @@ def main():
         host = host_leg(rgb, bt, tuning)
         print(f"[bench] host path: {json.dumps(host)}", file=sys.stderr, flush=True)
 
+    crowd = None
+    if not args.no_crowd:
+        crowd = crowd_leg(rgb)
+        print(f"[bench] crowd loop: {json.dumps(crowd)}", file=sys.stderr, flush=True)
+
     served = None
     if args.served_requests > 0:
         served = served_leg(rgb, gen, args.served_requests, args.served_load)
@@ -316,6 +376,7 @@ def main():
                      "kernel_ms_mean": kern_ms, "kernel_ms_median": kern_med},
         "cpu_baseline": cpu,
         "host_path": host,
+        "crowd_loop": crowd,
         "served": served,
     }
     print(json.dumps(line))

@@ -289,7 +289,10 @@ rgb_err_t rgb_solve_batch_host(rgb_ctx_t* ctx, int64_t num_lps, int64_t num_cons
  *      to `bounds`.
  * px, py, gx, gy, vx, vy, status: device arrays of n_agents.  Positions must
  * lie inside `bounds` (the kNN search relies on it; step 5 keeps them there).
- * `step` (0 .. 2^23 - 1) feeds the row-order keys; opts as for
+ * `step` (0 .. 2^23 - 1) feeds the row-order keys; step = -1 takes it from
+ * the crowd's device step counter (0 at creation) and advances the counter,
+ * so that a step captured in a HIP graph is a new step on every replay (the
+ * step allocates nothing and records no memset).  opts as for
  * rgb_solve_batch without n_1dlp_out or events.  Errors: INVALID_ARG, DEVICE.
  * ------------------------------------------------------------------------- */
 typedef struct rgb_crowd rgb_crowd_t;

@@ -54,38 +54,70 @@ __global__ void k_grid_count(const float* px, const float* py, int64_t n, Grid g
     atomicAdd(&count[c], 1);
 }
 
-// Exclusive scan of count[0 .. C) into start[0 .. C] and cursor[0 .. C), one
-// block of 1024 threads, each over a contiguous run of cells.
-__global__ __launch_bounds__(1024) void k_grid_scan(const int32_t* count, int64_t C, int32_t* start,
-                                                    int32_t* cursor) {
-    __shared__ int32_t part[1024];
+// Exclusive scan of count[0 .. C) into start[0 .. C] and cursor[0 .. C) in
+// three passes over tiles of 1024 cells: tile sums, their scan (one block),
+// then each tile's scan plus its offset.
+constexpr int kTile = 1024;
+
+__device__ __forceinline__ int32_t block_incl_scan(int32_t v, int32_t* sh) {
     const int t = threadIdx.x;
-    const int64_t per = (C + 1023) / 1024;
-    const int64_t lo = t * per, hi = lo + per < C ? lo + per : C;
-    int32_t sum = 0;
-    for (int64_t c = lo; c < hi; ++c) sum += count[c];
-    part[t] = sum;
+    sh[t] = v;
     __syncthreads();
-    for (int d = 1; d < 1024; d <<= 1) {
-        int32_t v = t >= d ? part[t - d] : 0;
+    for (int d = 1; d < kTile; d <<= 1) {
+        int32_t u = t >= d ? sh[t - d] : 0;
         __syncthreads();
-        part[t] += v;
+        sh[t] += u;
         __syncthreads();
     }
-    int32_t run = part[t] - sum;
-    for (int64_t c = lo; c < hi; ++c) {
-        start[c] = run;
-        cursor[c] = run;
-        run += count[c];
-    }
-    if (t == 1023) start[C] = part[1023];
+    return sh[t];
 }
 
-__global__ void k_grid_scatter(const int32_t* cell, int64_t n, int32_t* cursor, int32_t* sorted) {
+__global__ __launch_bounds__(kTile) void k_scan_tiles(const int32_t* count, int64_t C, int32_t* tile_sum) {
+    __shared__ int32_t sh[kTile];
+    const int64_t c = (int64_t)blockIdx.x * kTile + threadIdx.x;
+    const int32_t incl = block_incl_scan(c < C ? count[c] : 0, sh);
+    if (threadIdx.x == kTile - 1) tile_sum[blockIdx.x] = incl;
+}
+
+// One block: exclusive scan of the tile sums in place, each thread over a run.
+__global__ __launch_bounds__(kTile) void k_scan_tile_sums(int32_t* tile_sum, int64_t T, int32_t* start, int64_t C) {
+    __shared__ int32_t sh[kTile];
+    const int t = threadIdx.x;
+    const int64_t per = (T + kTile - 1) / kTile;
+    const int64_t lo = t * per, hi = lo + per < T ? lo + per : T;
+    int32_t sum = 0;
+    for (int64_t q = lo; q < hi; ++q) sum += tile_sum[q];
+    int32_t run = block_incl_scan(sum, sh) - sum;
+    for (int64_t q = lo; q < hi; ++q) {
+        const int32_t v = tile_sum[q];
+        tile_sum[q] = run;
+        run += v;
+    }
+    if (t == kTile - 1) start[C] = run;
+}
+
+__global__ __launch_bounds__(kTile) void k_scan_apply(const int32_t* count, int64_t C, const int32_t* tile_sum,
+                                                      int32_t* start, int32_t* cursor) {
+    __shared__ int32_t sh[kTile];
+    const int64_t c = (int64_t)blockIdx.x * kTile + threadIdx.x;
+    const int32_t v = c < C ? count[c] : 0;
+    const int32_t excl = block_incl_scan(v, sh) - v + tile_sum[blockIdx.x];
+    if (c < C) {
+        start[c] = excl;
+        cursor[c] = excl;
+    }
+}
+
+// Agents in cell order, with their positions next to them (one load each
+// when a neighbour search walks a cell).
+__global__ void k_grid_scatter(const int32_t* cell, const float* px, const float* py, int64_t n, int32_t* cursor,
+                               int32_t* sorted, float* spx, float* spy) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     int pos = atomicAdd(&cursor[cell[i]], 1);
     sorted[pos] = (int32_t)i;
+    spx[pos] = px[i];
+    spy[pos] = py[i];
 }
 
 // SplitMix64 (Steele, Lea and Flood 2014; constants as published by Vigna):
@@ -133,8 +165,10 @@ __device__ __forceinline__ int keep_best(uint64_t* s, int n, int keep) {
 __global__ __launch_bounds__(64 * kWaves) void k_crowd_build(const float* px, const float* py, const int32_t* kk,
                                                              const int64_t* offsets, int64_t n, Grid g,
                                                              const int32_t* start, const int32_t* sorted,
+                                                             const float* spx, const float* spy,
                                                              const float* disc, int n_disc, float radius,
-                                                             uint64_t seed, int64_t step, float* ax, float* ay,
+                                                             uint64_t seed, int64_t step_host,
+                                                             const int64_t* step_dev, float* ax, float* ay,
                                                              float* bb) {
     __shared__ uint64_t cand_all[kWaves][kCand];
     __shared__ uint64_t key_all[kWaves][kSlots];
@@ -147,18 +181,29 @@ __global__ __launch_bounds__(64 * kWaves) void k_crowd_build(const float* px, co
     const float pxi = px[i], pyi = py[i];
     const int ki = kk[i];
     const int cx = cell_of(pxi, g.x0, g.inv_h, g.W), cy = cell_of(pyi, g.y0, g.inv_h, g.H);
-    const int rmax = max(max(cx, g.W - 1 - cx), max(cy, g.H - 1 - cy));
+    const int rmax = max(max(max(cx, g.W - 1 - cx), max(cy, g.H - 1 - cy)), 2);
 
-    // k nearest: rings of cells at Chebyshev distance r, nearest ring first.
-    // Agents beyond ring r are at least r h away, so the search ends once the
-    // k-th best squared distance is clearly below (r h)^2.
+    // k nearest.  Cells are visited in batches, one cell per lane: first the
+    // (2 R0 + 1)^2 block around the agent's cell, then one ring of cells at
+    // Chebyshev distance r at a time (at most 64 cells per pass).  The lanes
+    // walk their cells' members in step, so a batch costs as many loads in a
+    // row as its fullest cell has members.  Agents beyond ring r are at least
+    // r h away, so the search ends once the k-th best squared distance is
+    // clearly below (r h)^2.
+    constexpr int R0 = 2;
+    constexpr int kBlockCells = (2 * R0 + 1) * (2 * R0 + 1);
     int nc = 0;
-    for (int r = 0; r <= rmax; ++r) {
-        const int side = r == 0 ? 1 : 8 * r;  // cells in ring r
-        for (int q = 0; q < side; ++q) {
-            int dx, dy;
-            if (r == 0) {
-                dx = dy = 0;
+    uint64_t worst = kNone;  // k-th best key so far (once k are known): no larger key can be kept
+    bool ready = false;      // cand[0 .. nc) is sorted and nc <= ki
+    for (int r = R0; ; ++r) {
+        const int first = r == R0;
+        const int ncells = first ? kBlockCells : 8 * r;
+        for (int base = 0; base < ncells; base += 64) {
+            const int q = base + lane;
+            int dx = 0, dy = 0;
+            if (first) {
+                dx = q % (2 * R0 + 1) - R0;
+                dy = q / (2 * R0 + 1) - R0;
             } else if (q < 2 * r + 1) {  // bottom row
                 dx = q - r;
                 dy = -r;
@@ -173,39 +218,49 @@ __global__ __launch_bounds__(64 * kWaves) void k_crowd_build(const float* px, co
                 dy = q - (6 * r + 1) - r + 1;
             }
             const int X = cx + dx, Y = cy + dy;
-            if (X < 0 || X >= g.W || Y < 0 || Y >= g.H) continue;
-            const int c = Y * g.W + X;
-            const int s = start[c], e = start[c + 1];
-            for (int base = s; base < e; base += 64) {
-                const int t = base + lane;
-                int j = t < e ? sorted[t] : -1;
-                bool v = j >= 0 && j != (int)i;
+            int s = 0, cnt = 0;
+            if (q < ncells && X >= 0 && X < g.W && Y >= 0 && Y < g.H) {
+                const int c = Y * g.W + X;
+                s = start[c];
+                cnt = start[c + 1] - s;
+            }
+            for (int m = 0; __ballot(m < cnt) != 0; ++m) {
+                bool v = m < cnt;
                 uint64_t key = kNone;
                 if (v) {
-                    const float ddx = px[j] - pxi, ddy = py[j] - pyi;
+                    const int j = sorted[s + m];
+                    const float ddx = spx[s + m] - pxi, ddy = spy[s + m] - pyi;
                     const float d2 = ddx * ddx + ddy * ddy;
                     key = ((uint64_t)__builtin_bit_cast(uint32_t, d2) << 32) | (uint32_t)j;
+                    v = j != (int)i && key < worst;
                 }
                 const uint64_t bal = __ballot(v);
-                const int cnt = __popcll(bal);
-                if (nc + cnt > kCand) nc = keep_best(cand, nc, ki);
+                const int cntv = __popcll(bal);
+                if (cntv > 0) ready = false;
+                if (nc + cntv > kCand) nc = keep_best(cand, nc, ki);
                 const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
                                                            __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0));
                 if (v) cand[nc + rank] = key;
                 __atomic_signal_fence(__ATOMIC_SEQ_CST);
-                nc += cnt;
+                nc += cntv;
             }
         }
-        if (r > 0 && nc >= ki) {
-            nc = keep_best(cand, nc, ki);
-            const float dk2 = __builtin_bit_cast(float, (uint32_t)(cand[ki - 1] >> 32));
+        if (r >= rmax) break;  // every cell visited
+        if (nc >= ki) {
+            if (!ready) {
+                nc = keep_best(cand, nc, ki);
+                ready = true;
+            }
+            worst = cand[ki - 1];
+            const float dk2 = __builtin_bit_cast(float, (uint32_t)(worst >> 32));
             const float lim = (float)r * g.h - 2.0f * g.fuzz;  // unvisited agents are farther than this
             if (lim > 0.0f && dk2 < lim * lim * 0.999999f) break;
         }
     }
-    nc = keep_best(cand, nc, ki);  // sorted; nc == ki (the batch has more than ki agents)
+    if (!ready) nc = keep_best(cand, nc, ki);  // sorted; nc == ki (the batch has more than ki agents)
 
     // rows: neighbours, then the speed disc; keys put them in random order
+    const int64_t step = step_host >= 0 ? step_host : *step_dev;
     const int m = ki + n_disc;
     float* rx = row_all[w][0];
     float* ry = row_all[w][1];
@@ -244,8 +299,9 @@ __global__ __launch_bounds__(64 * kWaves) void k_crowd_build(const float* px, co
 }
 
 __global__ void k_crowd_integrate(float* px, float* py, float* vx, float* vy, const int32_t* status, int64_t n,
-                                  float dt, Grid g) {
+                                  float dt, Grid g, int64_t* advance) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0 && advance) *advance += 1;  // the device step counter (read by this step's build)
     if (i >= n) return;
     float ux = vx[i], uy = vy[i];
     if (status[i] != 0) ux = uy = 0.0f;  // no feasible velocity: stand still
@@ -272,6 +328,9 @@ struct rgb_crowd {
     int64_t* offsets = nullptr;
     float *ax = nullptr, *ay = nullptr, *b = nullptr, *disc = nullptr;
     int32_t *cell = nullptr, *count = nullptr, *start = nullptr, *cursor = nullptr, *sorted = nullptr;
+    int32_t* tile_sum = nullptr;
+    float *spx = nullptr, *spy = nullptr;
+    int64_t* counter = nullptr;  // device step counter (step = -1)
 };
 
 extern "C" {
@@ -326,8 +385,9 @@ rgb_err_t rgb_crowd_create(rgb_ctx_t* ctx, int64_t n_agents, const int32_t* k, c
     auto al = [](size_t v) { return (v + 255) & ~size_t(255); };
     const size_t n_ = (size_t)n_agents, R = (size_t)c->rows, C = (size_t)c->cells;
     const size_t sz_k = al(4 * n_), sz_off = al(8 * (n_ + 1)), sz_row = al(4 * R), sz_disc = al(4 * (2 * kMaxDisc + 1)),
-                 sz_cell = al(4 * n_), sz_cnt = al(4 * (C + 1)), sz_sorted = al(4 * n_);
-    const size_t total = sz_k + sz_off + 3 * sz_row + sz_disc + sz_cell + 3 * sz_cnt + sz_sorted;
+                 sz_cell = al(4 * n_), sz_cnt = al(4 * (C + 1)), sz_sorted = al(4 * n_), sz_ctr = al(8),
+                 sz_tiles = al(4 * ((C + kTile - 1) / kTile));
+    const size_t total = sz_k + sz_off + 3 * sz_row + sz_disc + sz_cell + 3 * sz_cnt + 3 * sz_sorted + sz_ctr + sz_tiles;
     int prev = 0;
     if (hipGetDevice(&prev) != hipSuccess) {
         delete c;
@@ -353,7 +413,11 @@ rgb_err_t rgb_crowd_create(rgb_ctx_t* ctx, int64_t n_agents, const int32_t* k, c
         c->count = reinterpret_cast<int32_t*>(p); p += sz_cnt;
         c->start = reinterpret_cast<int32_t*>(p); p += sz_cnt;
         c->cursor = reinterpret_cast<int32_t*>(p); p += sz_cnt;
-        c->sorted = reinterpret_cast<int32_t*>(p);
+        c->sorted = reinterpret_cast<int32_t*>(p); p += sz_sorted;
+        c->spx = reinterpret_cast<float*>(p); p += sz_sorted;
+        c->spy = reinterpret_cast<float*>(p); p += sz_sorted;
+        c->tile_sum = reinterpret_cast<int32_t*>(p); p += sz_tiles;
+        c->counter = reinterpret_cast<int64_t*>(p);
         // the disc: unit normals at angles 2 pi q / n_disc, offset vmax
         std::vector<float> disc(2 * kMaxDisc + 1, 0.0f);
         for (int q = 0; q < o.n_disc; ++q) {
@@ -364,7 +428,8 @@ rgb_err_t rgb_crowd_create(rgb_ctx_t* ctx, int64_t n_agents, const int32_t* k, c
         disc[2 * o.n_disc] = o.vmax;
         if (hipMemcpy(c->k, k, 4 * n_, hipMemcpyHostToDevice) != hipSuccess ||
             hipMemcpy(c->offsets, offs.data(), 8 * (n_ + 1), hipMemcpyHostToDevice) != hipSuccess ||
-            hipMemcpy(c->disc, disc.data(), 4 * disc.size(), hipMemcpyHostToDevice) != hipSuccess)
+            hipMemcpy(c->disc, disc.data(), 4 * disc.size(), hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemset(c->counter, 0, 8) != hipSuccess)
             rc = RGB_ERR_DEVICE;
     }
     if (c->device != prev) (void)hipSetDevice(prev);
@@ -378,7 +443,7 @@ rgb_err_t rgb_crowd_create(rgb_ctx_t* ctx, int64_t n_agents, const int32_t* k, c
 
 rgb_err_t rgb_crowd_step(rgb_crowd_t* c, float* px, float* py, const float* gx, const float* gy, float* vx, float* vy,
                          int32_t* status, int64_t step, const rgb_solve_opts_t* opts, void* stream) {
-    if (!c || !px || !py || !gx || !gy || !vx || !vy || !status || step < 0 || step >= (int64_t(1) << 23))
+    if (!c || !px || !py || !gx || !gy || !vx || !vy || !status || step < -1 || step >= (int64_t(1) << 23))
         return RGB_ERR_INVALID_ARG;
     if (opts && (opts->n_1dlp_out || opts->ev_begin || opts->ev_end)) return RGB_ERR_INVALID_ARG;
     int prev = 0;
@@ -389,17 +454,24 @@ rgb_err_t rgb_crowd_step(rgb_crowd_t* c, float* px, float* py, const float* gx, 
     const unsigned nb = (unsigned)((n + 255) / 256);
     hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((C + 1 + 255) / 256)), dim3(256), 0, st, c->count, C + 1, 0);
     hipLaunchKernelGGL(k_grid_count, dim3(nb), dim3(256), 0, st, px, py, n, c->g, c->cell, c->count);
-    hipLaunchKernelGGL(k_grid_scan, dim3(1), dim3(1024), 0, st, c->count, C, c->start, c->cursor);
-    hipLaunchKernelGGL(k_grid_scatter, dim3(nb), dim3(256), 0, st, c->cell, n, c->cursor, c->sorted);
+    const int64_t T = (C + kTile - 1) / kTile;
+    hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)T), dim3(kTile), 0, st, c->count, C, c->tile_sum);
+    hipLaunchKernelGGL(k_scan_tile_sums, dim3(1), dim3(kTile), 0, st, c->tile_sum, T, c->start, C);
+    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)T), dim3(kTile), 0, st, c->count, C, c->tile_sum, c->start,
+                       c->cursor);
+    hipLaunchKernelGGL(k_grid_scatter, dim3(nb), dim3(256), 0, st, c->cell, px, py, n, c->cursor, c->sorted, c->spx,
+                       c->spy);
     hipLaunchKernelGGL(k_crowd_build, dim3((unsigned)((n + kWaves - 1) / kWaves)), dim3(64 * kWaves), 0, st, px, py,
-                       c->k, c->offsets, n, c->g, c->start, c->sorted, c->disc, c->o.n_disc, c->o.radius, c->o.seed,
-                       step, c->ax, c->ay, c->b);
+                       c->k, c->offsets, n, c->g, c->start, c->sorted, c->spx, c->spy, c->disc, c->o.n_disc,
+                       c->o.radius, c->o.seed,
+                       step, c->counter, c->ax, c->ay, c->b);
     rgb_err_t rc = hipGetLastError() == hipSuccess ? RGB_OK : RGB_ERR_DEVICE;
     if (rc == RGB_OK)
         rc = rgb_solve_batch(c->ctx, n, c->rows, c->offsets, c->ax, c->ay, c->b, gx, gy, vx, vy, status, opts,
                              stream);
     if (rc == RGB_OK) {
-        hipLaunchKernelGGL(k_crowd_integrate, dim3(nb), dim3(256), 0, st, px, py, vx, vy, status, n, c->o.dt, c->g);
+        hipLaunchKernelGGL(k_crowd_integrate, dim3(nb), dim3(256), 0, st, px, py, vx, vy, status, n, c->o.dt, c->g,
+                           step < 0 ? c->counter : nullptr);
         if (hipGetLastError() != hipSuccess) rc = RGB_ERR_DEVICE;
     }
     if (c->device != prev) (void)hipSetDevice(prev);

@@ -113,3 +113,53 @@ def test_full_size_step_sampled(oracle_lib):
     bs, bx = lpcheck.compare(status, ux, uy, o["status"], o["x"], o["y"])
     assert len(bs) == 0 and len(bx) == 0
     crowd.close()
+
+
+def test_crowd_step_as_a_graph():
+    """A step captured with step = -1 (the crowd's device step counter) and
+    replayed equals eager steps 0, 1, 2 bit for bit, with eager work and host
+    synchronisation between the replays."""
+    import torch
+    import paper_1902_04995_amd as rgb
+    n = 3000
+    px, py, k, gx, gy, bounds = _crowd(n, seed=5, density=2.0)
+    t = lambda a: torch.from_numpy(a).cuda()
+    dgx, dgy = t(gx), t(gy)
+
+    def buffers():
+        vx = torch.empty(n, dtype=torch.float32, device="cuda")
+        return t(px), t(py), vx, torch.empty_like(vx), torch.empty(n, dtype=torch.int32, device="cuda")
+
+    eager = rgb.Crowd(k, bounds, **OPTS)
+    ex, ey, evx, evy, est = buffers()
+    want = []
+    for s in range(3):
+        eager.step(ex, ey, dgx, dgy, evx, evy, est, s)
+        torch.cuda.synchronize()
+        want.append((ex.cpu().numpy(), ey.cpu().numpy(), est.cpu().numpy()))
+    eager.close()
+
+    crowd = rgb.Crowd(k, bounds, **OPTS)
+    gpx, gpy, vx, vy, st = buffers()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        crowd.step(gpx, gpy, dgx, dgy, vx, vy, st, 0, stream=side)  # warm-up: workspaces exist before capture
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=side):
+        crowd.step(gpx, gpy, dgx, dgy, vx, vy, st, -1, stream=side)
+    torch.cuda.synchronize()
+    gpx.copy_(t(px))
+    gpy.copy_(t(py))
+    torch.cuda.synchronize()
+    for s in range(3):
+        _say(f"[gpu] crowd graph replay {s}")
+        vx.fill_(-5.0)  # eager work between replays
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        got = (gpx.cpu().numpy(), gpy.cpu().numpy(), st.cpu().numpy())
+        for a, b in zip(got, want[s]):
+            assert np.array_equal(a, b), s
+    crowd.close()

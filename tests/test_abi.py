@@ -47,8 +47,10 @@ def test_binding_signatures_match_header():
     L = rgb.lib()
     for name, n in _declared().items():
         f = getattr(L, name)
-        if f.argtypes is not None:
-            assert len(f.argtypes) == n, (name, len(f.argtypes), n)
+        if name == "rgb_version":  # no parameters: ctypes leaves argtypes unset
+            continue
+        assert f.argtypes is not None, f"{name} has no ctypes signature in the binding"
+        assert len(f.argtypes) == n, (name, len(f.argtypes), n)
 
 
 def test_version_string_without_gpu():
@@ -63,3 +65,27 @@ def test_null_context_errors_without_gpu():
     assert L.rgb_ctx_last_error(None) == b"null context"
     assert L.rgb_ctx_destroy(None) == 0
     assert L.rgb_ctx_create(0, None) == -1
+
+
+def test_null_handles_are_rejected_without_gpu():
+    """Every entry point checks its handle and arguments before any HIP call."""
+    import paper_1902_04995_amd as rgb
+    L = rgb.lib()
+    ERR, OK = -1, 0
+    assert L.rgb_autotune(None, 0, 0, *([None] * 9), 1, 1.0, None, None) == ERR
+    assert L.rgb_plan_create(None, 0, 0, *([None] * 9), None, None) == ERR
+    assert L.rgb_plan_launch(None, None) == ERR
+    assert L.rgb_plan_destroy(None) == OK
+    assert L.rgb_ctx_get_tuning(None, None) == ERR
+    assert L.rgb_server_create(None, None, None) == ERR
+    assert L.rgb_server_submit(None, 0, 0, *([None] * 6), None) == ERR
+    assert L.rgb_server_poll(None, 0, 0, None, None, None, None, None) == ERR
+    assert L.rgb_server_destroy(None) == OK
+    assert L.rgb_solve_batch_host(None, 0, 0, *([None] * 9), None, 0, None) == ERR
+    assert L.rgb_crowd_create(None, 10, None, None, None, None) == ERR
+    assert L.rgb_crowd_step(None, *([None] * 7), 0, None, None) == ERR
+    assert L.rgb_crowd_num_rows(None, None) == ERR
+    assert L.rgb_crowd_rows(None, None, None, None, None, None) == ERR
+    assert L.rgb_crowd_destroy(None) == OK
+    # contention 3 is not a power of two: refused before anything is launched
+    assert L.rgb_reduce_bench_run(2, 3, 0, None, None, None) == ERR

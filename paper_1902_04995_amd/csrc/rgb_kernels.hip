@@ -345,7 +345,22 @@ __device__ __forceinline__ void solve_group(const Problem& P, int64_t lp, int lg
                 Line L;
                 make_line(L, lx, ly, lb);
                 float hi = __builtin_huge_valf(), lo = -__builtin_huge_valf();
-                for (int h = gl; h < v; h += G) work_unit(R.x(h), R.y(h), R.c(h), L, hi, lo);
+                if (v > 2 * G) {  // long 1D LPs: four units per lane per step, loads issued together
+                    for (int h = gl; h < v; h += 4 * G) {
+                        float x[4], y[4], c[4];
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) {
+                            int hk = h + k * G < v ? h + k * G : v - 1;
+                            x[k] = R.x(hk);
+                            y[k] = R.y(hk);
+                            c[k] = R.c(hk);
+                        }
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) work_unit(x[k], y[k], c[k], L, hi, lo);
+                    }
+                } else {
+                    for (int h = gl; h < v; h += G) work_unit(R.x(h), R.y(h), R.c(h), L, hi, lo);
+                }
                 hi = group_min(hi, lg);
                 lo = group_max(lo, lg);
                 settle_1dlp(st, R, v, L, hi, lo, cx, cy, gl, lg, gmask);

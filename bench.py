@@ -27,10 +27,10 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, public spec
 # Keyed by (kernel, workload) and valid only for the kernel sources whose
 # digest is recorded: after any kernel change the figure is reported as null.
 MEASURED_TRAFFIC = {
-    "sources": "21e9e5cf2c0f6e12",
-    ('k_pool<8, 2>', 'uniform'): 1773484993,
-    ('k_group<8>', 'crowd'): 490531015,
-    ('k_binned', 'uneven'): 9142475879,
+    "sources": "fa3f174535e615dd",
+    ('k_group<16>', 'uniform'): 1239964959,
+    ('k_group<8>', 'crowd'): 445854355,
+    ('k_binned', 'uneven'): 8794949446,
 }
 
 

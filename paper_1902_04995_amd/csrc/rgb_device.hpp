@@ -157,18 +157,65 @@ __device__ __forceinline__ bool parallel_empties(float ax, float ay, float b, co
     return N < 0.0;
 }
 
-// One work unit (Sec. 3): fold row (ax, ay, b) into the bounds on line L.
-// hi = min over right bounds (u_right), lo = max over left bounds (u_left).
-// Rows with D >= 0 count as right bounds, so a parallel row (D = 0) gives
-// sigma = r * (1/0) = +-inf: harmless when +inf (or NaN for r = 0), and -inf
-// when it may empty the line.  hi = -inf therefore flags "look again": the
-// caller reruns the rows with exact_pass(), which decides parallel rows in
-// FP64.  Ties and NaN positions leave a bound unchanged.
-__device__ __forceinline__ void work_unit(float ax, float ay, float b, const Line& L, float& hi, float& lo) {
+// IEEE minNum / maxNum as single instructions.  Their operands are always
+// results of arithmetic (never signalling NaNs), so none of the quieting the
+// compiler adds around fminf / fmaxf is needed; a quiet NaN operand is dropped.
+__device__ __forceinline__ float vmin(float a, float b) {
+    float r;
+    asm("v_min_f32 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+__device__ __forceinline__ float vmax(float a, float b) {
+    float r;
+    asm("v_max_f32 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+__device__ __forceinline__ float vmin3(float a, float b, float c) {
+    float r;
+    asm("v_min3_f32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
+}
+__device__ __forceinline__ float vmax3(float a, float b, float c) {
+    float r;
+    asm("v_max3_f32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
+}
+
+// One work unit (Sec. 3) as candidates: the row's position if it bounds from
+// the right (else hi, the neutral value) and if it bounds from the left (else
+// lo).  Rows with D >= 0 count as right bounds, so a parallel row (D = 0)
+// gives sigma = r * (1/0) = +-inf: harmless when +inf (or NaN for r = 0), and
+// -inf when it may empty the line.  hi = -inf therefore flags "look again":
+// the caller reruns the rows with work_unit_exact(), which decides parallel
+// rows in FP64.  A NaN position leaves a bound unchanged, and a tie only picks
+// the sign of a zero bound, which no later test or output depends on.
+__device__ __forceinline__ void wu_candidates(float ax, float ay, float b, const Line& L, float hi, float lo,
+                                              float& th, float& tl) {
     float D;
     float sig = wu_sigma(ax, ay, b, L, D);
-    hi = (D >= 0.0f && sig < hi) ? sig : hi;
-    lo = (D < 0.0f && sig > lo) ? sig : lo;
+    bool right = D >= 0.0f;
+    th = right ? sig : hi;
+    tl = right ? lo : sig;
+}
+
+// Fold one row into the bounds on line L: hi = min over right bounds
+// (u_right), lo = max over left bounds (u_left).
+__device__ __forceinline__ void work_unit(float ax, float ay, float b, const Line& L, float& hi, float& lo) {
+    float th, tl;
+    wu_candidates(ax, ay, b, L, hi, lo, th, tl);
+    hi = vmin(hi, th);
+    lo = vmax(lo, tl);
+}
+
+// Four work units folded with v_min3 / v_max3 (the same bounds as four
+// work_unit calls: min and max are exact and order-free).
+__device__ __forceinline__ void work_units4(const float (&x)[4], const float (&y)[4], const float (&c)[4], const Line& L,
+                                            float& hi, float& lo) {
+    float th[4], tl[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) wu_candidates(x[k], y[k], c[k], L, hi, lo, th[k], tl[k]);
+    hi = vmin3(vmin3(hi, th[0], th[1]), th[2], th[3]);
+    lo = vmax3(vmax3(lo, tl[0], tl[1]), tl[2], tl[3]);
 }
 
 // The careful version of work_unit for the rare rerun: parallel rows are

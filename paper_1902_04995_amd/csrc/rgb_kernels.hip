@@ -355,8 +355,7 @@ __device__ __forceinline__ void solve_group(const Problem& P, int64_t lp, int lg
                             y[k] = R.y(hk);
                             c[k] = R.c(hk);
                         }
-#pragma unroll
-                        for (int k = 0; k < 4; ++k) work_unit(x[k], y[k], c[k], L, hi, lo);
+                        work_units4(x, y, c, L, hi, lo);
                     }
                 } else {
                     for (int h = gl; h < v; h += G) work_unit(R.x(h), R.y(h), R.c(h), L, hi, lo);
@@ -492,8 +491,7 @@ __device__ __forceinline__ void pool_work_units(const Problem& P, PoolLds& S, in
                 y[k] = R.y(hk);
                 c[k] = R.c(hk);
             }
-#pragma unroll
-            for (int k = 0; k < 4; ++k) work_unit(x[k], y[k], c[k], L, hi, lo);
+            work_units4(x, y, c, L, hi, lo);
         }
         if (hi != __builtin_huge_valf())
             __hip_atomic_fetch_min(&S.g[g].hi, fkey(hi), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);

@@ -8,7 +8,11 @@ Contents
                      LP ranges by Python threads (ctypes drops the GIL).
   * ``brute_force`` - exact rational vertex enumeration for one small LP; the
                      pin the oracle is checked against.
-  * ``build``      - compiles ``seidel_oracle.c`` with gcc.
+  * ``solve3``     - 3D LPs inside a box: FP64 vertex enumeration in C
+                     (``lp3_oracle.c``), the definition written out.
+  * ``brute_force3`` - the same definition in exact rational arithmetic for
+                     one small LP.
+  * ``build``      - compiles both C files with gcc.
 """
 from __future__ import annotations
 
@@ -26,17 +30,21 @@ STATUS_NAMES = {OPTIMAL: "optimal", INFEASIBLE: "infeasible", UNBOUNDED: "unboun
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "seidel_oracle.c")
 _LIB = os.path.join(_HERE, "librgb_oracle.so")
+_SRC3 = os.path.join(_HERE, "lp3_oracle.c")
+_LIB3 = os.path.join(_HERE, "librgb_oracle3.so")
 _lib = None
+_lib3 = None
 
 
 def build(force: bool = True) -> str:
     """Compile the oracle.  -ffp-contract=off keeps every product and sum
     rounded as written (no fused multiply-add)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
-                               "-shared", "-o", tmp, _SRC, "-lm"])
-        os.replace(tmp, _LIB)
+    for src, lib in ((_SRC, _LIB), (_SRC3, _LIB3)):
+        if force or not os.path.exists(lib) or os.path.getmtime(lib) < os.path.getmtime(src):
+            tmp = lib + ".tmp"
+            subprocess.check_call(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
+                                   "-shared", "-o", tmp, src, "-lm"])
+            os.replace(tmp, lib)
     return _LIB
 
 
@@ -183,3 +191,121 @@ def brute_force_batch(batch):
         s, e = int(batch.offsets[k]), int(batch.offsets[k + 1])
         res.append(brute_force(batch.ax[s:e], batch.ay[s:e], batch.b[s:e], batch.cx[k], batch.cy[k]))
     return res
+
+
+# ---------------------------------------------------------------------------
+# Three dimensions: maximize c.x over R^3 subject to a_i.x <= b_i and
+# |x_k| <= M; the lexicographically smallest maximiser (smallest x, then y,
+# then z).  UNBOUNDED means the optimum lies on a face of the box.
+# ---------------------------------------------------------------------------
+
+def _load3():
+    global _lib3
+    if _lib3 is None:
+        if not os.path.exists(_LIB3) or os.path.getmtime(_LIB3) < os.path.getmtime(_SRC3):
+            build(force=False)
+        lib = ctypes.CDLL(_LIB3)
+        f = lib.rgb_oracle3_solve_range
+        P = ctypes.c_void_p
+        f.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_int64] + [P] * 8 + [ctypes.c_double] + [P] * 3
+        f.restype = ctypes.c_int
+        _lib3 = lib
+    return _lib3
+
+
+def solve3(batch, threads: int | None = None, lp_begin: int = 0, lp_end: int | None = None):
+    """Solve LPs [lp_begin, lp_end) of a ``gen3.Batch3``.  Returns a dict with
+    x (B, 3) float64, status (int32) and def (B, 3) int32 (the planes of the
+    optimal vertex: rows 0..m-1, box faces -1..-6), plus the thread count.
+    LPs are split over threads by equal sum of m^4 (the enumeration's cost)."""
+    lib = _load3()
+    offsets = np.ascontiguousarray(batch.offsets, dtype=np.int64)
+    arrs = [np.ascontiguousarray(getattr(batch, f), dtype=np.float32) for f in ("ax", "ay", "az", "b", "cx", "cy", "cz")]
+    B = offsets.shape[0] - 1
+    if lp_end is None:
+        lp_end = B
+    out = {"x": np.full((B, 3), np.nan), "status": np.full(B, INVALID, dtype=np.int32),
+           "def": np.full((B, 3), -100, dtype=np.int32)}
+    if threads is None:
+        threads = max(1, len(os.sched_getaffinity(0)))
+    n = lp_end - lp_begin
+    if n <= 0:
+        out["threads"] = 0
+        return out
+    threads = max(1, min(threads, n))
+    m = np.diff(offsets[lp_begin:lp_end + 1]).astype(np.float64) + 6.0
+    work = np.concatenate([[0.0], np.cumsum(m ** 4)])
+    cuts = np.searchsorted(work, np.linspace(0, work[-1], threads + 1)[1:-1]) + lp_begin
+    bounds = [lp_begin] + sorted(set(int(c) for c in cuts if lp_begin < c < lp_end)) + [lp_end]
+    N = int(batch.b.shape[0])
+    args = [_ptr(offsets)] + [_ptr(a) for a in arrs] + [ctypes.c_double(float(batch.box))] + \
+        [_ptr(out["x"]), _ptr(out["status"]), _ptr(out["def"])]
+
+    def run(s, e):
+        if e > s:
+            lib.rgb_oracle3_solve_range(s, e, N, *args)
+
+    ths = [threading.Thread(target=run, args=(bounds[i], bounds[i + 1])) for i in range(len(bounds) - 1)]
+    for t in ths:
+        t.start()
+    for t in ths:
+        t.join()
+    out["threads"] = len(ths)
+    return out
+
+
+def _det3(p, q, r):
+    return (p[0] * (q[1] * r[2] - q[2] * r[1]) - p[1] * (q[0] * r[2] - q[2] * r[0])
+            + p[2] * (q[0] * r[1] - q[1] * r[0]))
+
+
+def brute_force3(ax, ay, az, b, c, M):
+    """Exact rational vertex enumeration of one 3D LP inside the box |x_k| <= M.
+    Returns (status, (x, y, z) as Fractions or None)."""
+    if not all(np.isfinite(v) for v in list(ax) + list(ay) + list(az) + list(b) + list(c)) or \
+            not (np.isfinite(M) and M > 0):
+        return INVALID, None
+    Mf = _frac(M)
+    rows = []
+    for p, q, r, s in zip(ax, ay, az, b):
+        a = (_frac(p), _frac(q), _frac(r))
+        if a == (0, 0, 0):
+            if _frac(s) < 0:
+                return INFEASIBLE, None
+            continue
+        rows.append((a, _frac(s)))
+    for k in range(3):
+        for sgn in (1, -1):
+            e = [Fraction(0)] * 3
+            e[k] = Fraction(sgn)
+            rows.append((tuple(e), Mf))
+    cf = tuple(_frac(v) for v in c)
+    best = None
+    n = len(rows)
+    for i in range(n):
+        for j in range(i + 1, n):
+            for k in range(j + 1, n):
+                A, B, C = rows[i][0], rows[j][0], rows[k][0]
+                D = _det3(A, B, C)
+                if D == 0:
+                    continue
+                rhs = (rows[i][1], rows[j][1], rows[k][1])
+                v = []
+                for col in range(3):
+                    cols = [list(A), list(B), list(C)]
+                    for t in range(3):
+                        cols[t][col] = rhs[t]
+                    v.append(_det3(*cols) / D)
+                key = (sum(ci * vi for ci, vi in zip(cf, v)), -v[0], -v[1], -v[2])
+                if best is not None and key <= best[0]:
+                    continue
+                if all(sum(ai * vi for ai, vi in zip(a, v)) <= bb for a, bb in rows):
+                    best = (key, v)
+    if best is None:
+        return INFEASIBLE, None
+    v = best[1]
+    return (UNBOUNDED if max(abs(t) for t in v) == Mf else OPTIMAL), tuple(v)
+
+
+def brute_force3_batch(batch):
+    return [brute_force3(*batch.lp(k)[:4], batch.lp(k)[4], batch.box) for k in range(batch.num_lps)]

@@ -130,3 +130,59 @@ def check_unbounded_ray(ax, ay, b, cx, cy, l, dirn):
     if not key > (0, 0, 0):
         return "ray does not improve the objective"
     return None
+
+
+def parse_golden3(path):
+    """3D fixtures: lp NAME / c cx cy cz / box M / row ax ay az b ... /
+    expect optimal|unbounded x y z  or  expect infeasible / end."""
+    lps, cur = [], None
+    with open(path) as f:
+        for raw in f:
+            line = raw.split("#", 1)[0].strip()
+            if not line:
+                continue
+            tok = line.split()
+            if tok[0] == "lp":
+                cur = {"name": tok[1], "rows": [], "c": None, "box": None, "expect": None}
+            elif tok[0] == "c":
+                cur["c"] = tuple(float(t) for t in tok[1:4])
+            elif tok[0] == "box":
+                cur["box"] = float(tok[1])
+            elif tok[0] == "row":
+                cur["rows"].append(tuple(float(t) for t in tok[1:5]))
+            elif tok[0] == "expect":
+                st = {"optimal": OPTIMAL, "infeasible": INFEASIBLE, "unbounded": UNBOUNDED}[tok[1]]
+                xyz = tuple(float(t) for t in tok[2:5]) if st != INFEASIBLE else None
+                cur["expect"] = (st, xyz)
+            elif tok[0] == "end":
+                lps.append(cur)
+                cur = None
+    return lps
+
+
+def golden3_batch(lps):
+    """One Batch3 holding the fixtures (they must share one box)."""
+    from paper_1902_04995_amd import gen3
+    parts = []
+    for lp in lps:
+        rows = np.array(lp["rows"], dtype=np.float32).reshape(-1, 4)
+        offs = np.array([0, rows.shape[0]], dtype=np.int64)
+        c = np.array(lp["c"], dtype=np.float32)
+        parts.append(gen3.Batch3(offs, rows[:, 0].copy(), rows[:, 1].copy(), rows[:, 2].copy(), rows[:, 3].copy(),
+                                 c[:1], c[1:2], c[2:], np.zeros(1, np.int8), lp["box"], lp["name"]))
+    return parts
+
+
+def kkt_residual3(A, b, c, x, tight_tol=1e-7):
+    """Optimality certificate for a 3D LP without the box: the rows tight at x
+    (|a.x - b| <= tight_tol (1 + |b|)) must carry multipliers lambda >= 0 with
+    sum lambda a = c.  Returns (max violation of a.x <= b, relative residual of
+    the non-negative least-squares fit)."""
+    from scipy.optimize import nnls
+    slack = A @ x - b
+    viol = float(np.max(slack, initial=-np.inf))
+    tight = np.abs(slack) <= tight_tol * (1.0 + np.abs(b))
+    if not tight.any():
+        return viol, float(np.linalg.norm(c))
+    lam, res = nnls(A[tight].T, c)
+    return viol, float(res / max(1e-300, np.linalg.norm(c)))

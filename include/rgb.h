@@ -342,6 +342,40 @@ typedef enum {
 rgb_err_t rgb_reduce_bench_run(int32_t method, int32_t contention, int64_t n, const float* in, float* out,
                                void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Batched three-dimensional LPs (the method of Sec. 2.1 with n = 3; the paper
+ * names higher dimensions as its next step in Sec. 6).
+ *
+ * LP k: maximize c_k.x over x in R^3 subject to a_i.x <= b_i for its rows
+ * offsets[k] <= i < offsets[k+1], and the bounding rows |x_j| <= box of
+ * Sec. 2.1 (one box for the batch; the rows are not stored).  The result is
+ * the lexicographically smallest maximiser: among the points maximising c.x
+ * the one with the smallest x, then y, then z.  Rows are taken in the order
+ * given (the caller's random order gives Seidel's expected bound).
+ *
+ * Layout as rgb_solve_batch, with a third normal component: offsets int64
+ * [num_lps + 1]; ax, ay, az, b float [num_constraints]; cx, cy, cz float
+ * [num_lps]; outputs x, y, z float and status int32 [num_lps].  All pointers
+ * are DEVICE memory owned by the caller.  Status: OPTIMAL; INFEASIBLE (x
+ * NaN); UNBOUNDED when the optimum lies on a face of the box (the LP without
+ * the box is unbounded, or its optimum lies outside the box), with x the
+ * optimum inside the box; INVALID (x NaN) for non-finite rows or objective
+ * and offsets that are out of range, decreasing or span 2^30 rows or more.
+ * Arithmetic is FP64 on the FP32 inputs.
+ *
+ * lanes_per_lp: 0 (= 16) or 4, 8, 16, 32, 64 lanes per LP.  ev_begin,
+ * ev_end: optional hipEvent_t recorded on `stream` around the kernel.
+ * Enqueued on `stream` (0 = null stream) on ctx's device; returns before the
+ * solve completes.  Errors (synchronous, nothing enqueued): INVALID_ARG for
+ * a null context or pointer, negative sizes, box not finite and positive or
+ * an unsupported lanes_per_lp; TOO_LARGE above 2^31 - 1 LPs; DEVICE when
+ * the launch fails.
+ * ------------------------------------------------------------------------- */
+rgb_err_t rgb_solve3_batch(rgb_ctx_t* ctx, int64_t num_lps, int64_t num_constraints, const int64_t* offsets,
+                           const float* ax, const float* ay, const float* az, const float* b, const float* cx,
+                           const float* cy, const float* cz, double box, float* x_out, float* y_out, float* z_out,
+                           int32_t* status_out, int32_t lanes_per_lp, void* stream, void* ev_begin, void* ev_end);
+
 #ifdef __cplusplus
 }
 #endif

@@ -149,6 +149,8 @@ def lib():
         L.rgb_crowd_destroy.restype = I32
         L.rgb_reduce_bench_run.argtypes = [I32, I32, I64, P, P, P]
         L.rgb_reduce_bench_run.restype = I32
+        L.rgb_solve3_batch.argtypes = [P, I64, I64] + [P] * 8 + [ctypes.c_double] + [P] * 4 + [I32, P, P, P]
+        L.rgb_solve3_batch.restype = I32
         _lib = L
     return _lib
 
@@ -584,3 +586,60 @@ class Crowd:
             self.close()
         except Exception:
             pass
+
+
+# ---------------------------------------------------------------------------
+# Three-dimensional LPs (rgb_solve3_batch)
+# ---------------------------------------------------------------------------
+
+def solve3_batch(offsets, ax, ay, az, b, cx, cy, cz, box, *, lanes_per_lp=0, out=None, stream=None,
+                 ctx: Context | None = None, events=None):
+    """Solve a batch of 3D LPs held in CUDA tensors (offsets int64[B+1]; ax,
+    ay, az, b float32[N]; cx, cy, cz float32[B]) inside the box |x_k| <= box.
+    Enqueues on ``stream`` (default: torch's current stream) and returns
+    (x, y, z, status) tensors, valid once that stream has run the work.
+    ``events`` = (begin, end) torch.cuda.Events recorded around the kernel."""
+    import torch
+    dev = offsets.device
+    if dev.type != "cuda":
+        raise ValueError("solve3_batch needs CUDA tensors")
+    _check_tensor(offsets, "offsets", torch.int64, dev)
+    for name, t in (("ax", ax), ("ay", ay), ("az", az), ("b", b), ("cx", cx), ("cy", cy), ("cz", cz)):
+        _check_tensor(t, name, torch.float32, dev)
+    B = offsets.numel() - 1
+    N = ax.numel()
+    if B < 0 or ay.numel() != N or az.numel() != N or b.numel() != N or cx.numel() != B or cy.numel() != B \
+            or cz.numel() != B:
+        raise ValueError("inconsistent batch shapes")
+    if out is None:
+        out = tuple(torch.empty(B, dtype=torch.float32, device=dev) for _ in range(3)) + \
+            (torch.empty(B, dtype=torch.int32, device=dev),)
+    x, y, z, st = out
+    ctx = ctx or context(dev.index or 0)
+    if stream is None:
+        stream = torch.cuda.current_stream(dev)
+    ev = (None, None) if events is None else tuple(_event_handle(e) for e in events)
+    rc = lib().rgb_solve3_batch(ctx.handle, B, N, _ptr(offsets), _ptr(ax), _ptr(ay), _ptr(az), _ptr(b), _ptr(cx),
+                                _ptr(cy), _ptr(cz), ctypes.c_double(float(box)), _ptr(x), _ptr(y), _ptr(z), _ptr(st),
+                                int(lanes_per_lp), ctypes.c_void_p(stream.cuda_stream), ctypes.c_void_p(ev[0]),
+                                ctypes.c_void_p(ev[1]))
+    if rc != 0:
+        raise RgbError(f"rgb_solve3_batch failed ({rc})")
+    return out
+
+
+class DeviceBatch3:
+    """A gen3.Batch3 copied to device memory."""
+
+    def __init__(self, batch, device="cuda"):
+        import torch
+        t = lambda a: torch.from_numpy(a).to(device)
+        self.offsets = t(batch.offsets)
+        self.ax, self.ay, self.az, self.b = t(batch.ax), t(batch.ay), t(batch.az), t(batch.b)
+        self.cx, self.cy, self.cz = t(batch.cx), t(batch.cy), t(batch.cz)
+        self.box = float(batch.box)
+        self.num_lps = batch.num_lps
+        self.num_constraints = batch.num_constraints
+
+    def solve(self, **kw):
+        return solve3_batch(self.offsets, self.ax, self.ay, self.az, self.b, self.cx, self.cy, self.cz, self.box, **kw)

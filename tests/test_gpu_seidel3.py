@@ -1,0 +1,168 @@
+"""GPU parity of the 3D solver (rgb_solve3_batch) against the 3D oracle.
+
+Bar (per LP): status bit-exact; for OPTIMAL and UNBOUNDED (the optimum on the
+box) ||x - x_oracle||_inf <= 1e-4 * max(1, |x_oracle|) per component (an FP64
+solve rounded to FP32 against FP64 vertex enumeration).  Every lane width must
+give bit-identical results (the bound reductions are exact min/max with a
+smallest-index tie-break).
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import lpcheck
+from lpcheck import INFEASIBLE, INVALID, OPTIMAL, UNBOUNDED
+from paper_1902_04995_amd import gen3
+
+pytestmark = pytest.mark.gpu
+X_RTOL = 1e-4
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def rgb():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_1902_04995_amd as rgb
+    rgb.lib()
+    return rgb
+
+
+def _run(rgb, bt, g=0):
+    import torch
+    dev = rgb.DeviceBatch3(bt, "cuda:0")
+    x, y, z, st = dev.solve(lanes_per_lp=g)
+    torch.cuda.synchronize()
+    return st.cpu().numpy(), np.stack([x.cpu().numpy(), y.cpu().numpy(), z.cpu().numpy()], 1)
+
+
+def _mismatches(ref, st, x, idx=None):
+    rs, rx = ref["status"], ref["x"]
+    if idx is not None:
+        rs, rx = rs[idx], rx[idx]
+    bad_s = np.flatnonzero(st != rs)
+    has_x = (rs == OPTIMAL) | (rs == UNBOUNDED)
+    err = np.abs(x.astype(np.float64) - rx) > X_RTOL * np.maximum(1.0, np.abs(rx))
+    bad_x = np.flatnonzero(has_x & (st == rs) & err.any(axis=1))
+    return bad_s, bad_x
+
+
+def _check(bt, ref, st, x, label):
+    bs, bx = _mismatches(ref, st, x)
+    msg = f"{label}: {len(bs)} status / {len(bx)} x mismatches of {bt.num_lps}"
+    for k in list(bs[:5]) + list(bx[:5]):
+        msg += f"\n  lp {k} m={bt.sizes()[k]} got st={st[k]} x={x[k]} ref st={ref['status'][k]} x={ref['x'][k]}"
+    assert len(bs) + len(bx) == 0, msg
+
+
+BATCHES = {
+    "int_k2": lambda: gen3.tiny_integer_batch3(3000, m_max=8, K=2, seed=21),
+    "int_k3_boxed": lambda: gen3.tiny_integer_batch3(3000, m_max=10, K=3, seed=22, boxed=True),
+    "int_k1_boxed": lambda: gen3.tiny_integer_batch3(2000, m_max=12, K=1, seed=23, boxed=True),
+    "random": lambda: gen3.tiny_random_batch3(3000, m_max=40, seed=24),
+    "uniform3_small": lambda: gen3.uniform3_batch(2000, 64, seed=25),
+}
+
+
+@pytest.mark.parametrize("name", list(BATCHES))
+def test_seidel3_matches_oracle(rgb, oracle_lib, name):
+    bt = BATCHES[name]()
+    ref = oracle_lib.solve3(bt)
+    _say(f"[seidel3] {name}: {bt.num_lps} LPs, {bt.num_constraints} rows, status mix "
+         f"{np.bincount(ref['status'], minlength=4).tolist()}")
+    st, x = _run(rgb, bt)
+    _check(bt, ref, st, x, name)
+
+
+@pytest.mark.parametrize("g", [4, 8, 16, 32, 64])
+def test_seidel3_lane_widths_bit_identical(rgb, oracle_lib, g):
+    bt = gen3.concat3([gen3.uniform3_batch(700, 100, seed=26), gen3.uniform3_batch(300, 7, seed=27)])
+    st0, x0 = _run(rgb, bt, 16)
+    st, x = _run(rgb, bt, g)
+    assert np.array_equal(st, st0)
+    assert np.array_equal(x.view(np.int32), x0.view(np.int32))
+    if g == 4:
+        _check(bt, oracle_lib.solve3(bt), st, x, "uniform3 mix")
+
+
+def test_seidel3_hand_solved_golden(rgb):
+    lps = lpcheck.parse_golden3(os.path.join(lpcheck.GOLDEN, "lp3_hand.txt"))
+    for lp, bt in zip(lps, lpcheck.golden3_batch(lps)):
+        st, x = _run(rgb, bt)
+        want, xyz = lp["expect"]
+        assert st[0] == want, lp["name"]
+        if xyz is None:
+            assert np.isnan(x[0]).all(), lp["name"]
+        else:
+            np.testing.assert_allclose(x[0], xyz, rtol=1e-6, atol=1e-6, err_msg=lp["name"])
+
+
+def test_seidel3_edges(rgb, oracle_lib):
+    import torch
+    # empty batch: nothing enqueued, no error
+    z64 = torch.zeros(1, dtype=torch.int64, device="cuda")
+    e = torch.empty(0, dtype=torch.float32, device="cuda")
+    out = rgb.solve3_batch(z64, e, e, e, e, e, e, e, 10.0)
+    assert out[3].numel() == 0
+    # empty LPs, NaN rows, NaN objective, bad offsets
+    bt = gen3.tiny_random_batch3(40, m_max=12, m_min=0, seed=28)
+    sizes = bt.sizes()
+    ax = bt.ax.copy()
+    b = bt.b.copy()
+    cz = bt.cz.copy()
+    k1 = int(np.flatnonzero(sizes >= 3)[0])
+    k2 = int(np.flatnonzero(sizes >= 3)[1])
+    ax[bt.offsets[k1] + 2] = np.nan
+    b[bt.offsets[k2] + sizes[k2] - 1] = -np.inf
+    cz[5] = np.inf
+    bad = gen3.Batch3(bt.offsets, ax, bt.ay, bt.az, b, bt.cx, bt.cy, cz, bt.kind, bt.box)
+    ref = oracle_lib.solve3(bad)
+    st, x = _run(rgb, bad)
+    assert st[k1] == INVALID and st[k2] == INVALID and st[5] == INVALID
+    _check(bad, ref, st, x, "edges")
+    assert (sizes == 0).any() and (st[sizes == 0] == UNBOUNDED).all()
+    # offsets out of range, decreasing: INVALID, and nothing read out of range
+    dev = rgb.DeviceBatch3(bt, "cuda:0")
+    offs = dev.offsets.clone()
+    offs[3] = bt.num_constraints + 100
+    offs[7] = -5
+    x_, y_, z_, s_ = rgb.solve3_batch(offs, dev.ax, dev.ay, dev.az, dev.b, dev.cx, dev.cy, dev.cz, bt.box)
+    torch.cuda.synchronize()
+    s_ = s_.cpu().numpy()
+    assert s_[2] == INVALID and s_[3] == INVALID and s_[6] == INVALID and s_[7] == INVALID
+    # argument errors are synchronous and enqueue nothing
+    for box in (0.0, -1.0, float("inf"), float("nan")):
+        with pytest.raises(rgb.RgbError):
+            rgb.solve3_batch(dev.offsets, dev.ax, dev.ay, dev.az, dev.b, dev.cx, dev.cy, dev.cz, box)
+    with pytest.raises(rgb.RgbError):
+        dev.solve(lanes_per_lp=12)
+
+
+def test_seidel3_full_size_sampled(rgb, oracle_lib):
+    """The measurement workload (65,536 LPs x 128 planes) in one launch at the
+    default width; 384 sampled LPs against the oracle, and the status mix the
+    generator plants (5% infeasible, 2% on the box)."""
+    import torch
+    bt = gen3.make_config3("uniform3", seed=0)
+    st, x = _run(rgb, bt)
+    rng = np.random.default_rng(29)
+    idx = np.sort(rng.choice(bt.num_lps, 384, replace=False))
+    sub = bt.subset(idx)
+    ref = oracle_lib.solve3(sub)
+    bs, bx = _mismatches(ref, st[idx], x[idx])
+    assert len(bs) + len(bx) == 0, (bs[:5], bx[:5])
+    counts = np.bincount(st, minlength=4)
+    _say(f"[seidel3] full size status mix {counts.tolist()}")
+    assert counts[INFEASIBLE] == int(round(0.05 * bt.num_lps))
+    assert counts[UNBOUNDED] == int(round(0.02 * bt.num_lps))
+    assert counts[INVALID] == 0
+    # a second launch gives the same bits
+    st2, x2 = _run(rgb, bt)
+    assert np.array_equal(st2, st) and np.array_equal(x2.view(np.int32), x.view(np.int32))
+    torch.cuda.empty_cache()

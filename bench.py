@@ -221,6 +221,7 @@ def main():
     ap.add_argument("--served-load", type=float, default=0.7)
     ap.add_argument("--no-host", action="store_true", help="skip the host-to-host (transfer-inclusive) leg")
     ap.add_argument("--no-crowd", action="store_true", help="skip the crowd time-step leg")
+    ap.add_argument("--no-seidel3", action="store_true", help="skip the 3D solver leg")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -316,6 +317,12 @@ def main():
         crowd = crowd_leg(rgb)
         print(f"[bench] crowd loop: {json.dumps(crowd)}", file=sys.stderr, flush=True)
 
+    seidel3 = None
+    if not args.no_seidel3:
+        from paper_1902_04995_amd import gen3, seidel3_run
+        seidel3 = seidel3_run.measure(rgb, gen3.make_config3("uniform3", seed=0), steps=10)
+        print(f"[bench] 3D: {json.dumps(seidel3)}", file=sys.stderr, flush=True)
+
     served = None
     if args.served_requests > 0:
         served = served_leg(rgb, gen, args.served_requests, args.served_load)
@@ -377,6 +384,7 @@ def main():
         "cpu_baseline": cpu,
         "host_path": host,
         "crowd_loop": crowd,
+        "seidel3": seidel3,
         "served": served,
     }
     print(json.dumps(line))

@@ -1,0 +1,91 @@
+"""Time the 3D solver (rgb_solve3_batch) on the 3D measurement workload.
+
+    python -m paper_1902_04995_amd.seidel3_run [--steps K] [--lanes 8,16,32]
+
+Generates the seeded workload (65,536 LPs x 128 planes inside |x_k| <= 1e4),
+copies it to HBM, and for each lane width runs two warm-up launches and K
+timed ones, with HIP events recorded by the library around the kernel on the
+launch stream.  Prints one JSON line; ``measure`` is what ``bench.py`` calls.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import sys
+
+import numpy as np
+
+HBM_PEAK_GBS = 8000.0
+
+
+def measure(rgb, bt, lanes=(8, 16, 32), steps=10, log=None):
+    import torch
+    dev = rgb.DeviceBatch3(bt, "cuda:0")
+    stream = torch.cuda.current_stream()
+    out = tuple(torch.empty(bt.num_lps, dtype=torch.float32, device="cuda") for _ in range(3)) + \
+        (torch.empty(bt.num_lps, dtype=torch.int32, device="cuda"),)
+    per = {}
+    for g in lanes:
+        for _ in range(2):
+            dev.solve(lanes_per_lp=g, out=out, stream=stream)
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for a, b in evs:
+            dev.solve(lanes_per_lp=g, out=out, stream=stream, events=(a, b))
+        e1.record(stream)
+        torch.cuda.synchronize()
+        per[g] = {"ms_per_step": e0.elapsed_time(e1) / steps,
+                  "kernel_ms_mean": float(np.mean([a.elapsed_time(b) for a, b in evs]))}
+        if log:
+            log(f"[seidel3] lanes {g}: {per[g]['kernel_ms_mean']:.3f} ms per kernel")
+    best = min(per, key=lambda g: per[g]["kernel_ms_mean"])
+    # achievable-bandwidth context (and the counter calibration of a profile):
+    # a device copy of as many bytes as the solve reads and writes
+    n_copy = bt.algorithmic_bytes() // 8
+    src = torch.empty(n_copy, dtype=torch.float32, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    c0.record(stream)
+    for _ in range(5):
+        dst.copy_(src)
+    c1.record(stream)
+    torch.cuda.synchronize()
+    copy_ms = c0.elapsed_time(c1) / 5
+    copy_probe = {"bytes_moved": 8 * n_copy, "ms": copy_ms, "gbs": 8 * n_copy / (copy_ms / 1e3) / 1e9}
+    del src, dst
+    dev.solve(lanes_per_lp=best, out=out, stream=stream)
+    torch.cuda.synchronize()
+    status = np.bincount(out[3].cpu().numpy(), minlength=4).tolist()
+    alg = bt.algorithmic_bytes()
+    k_ms = per[best]["kernel_ms_mean"]
+    achieved = alg / (k_ms / 1e3) / 1e9
+    return {"workload": f"{bt.num_lps} LPs x {bt.num_constraints // max(1, bt.num_lps)} planes, box {bt.box:g}",
+            "num_lps": bt.num_lps, "planes": bt.num_constraints, "lanes_per_lp": best,
+            "lps_per_s": bt.num_lps / (per[best]["ms_per_step"] / 1e3), "ms_per_step": per[best]["ms_per_step"],
+            "kernel": f"k_seidel3<{best}>", "kernel_ms_mean": k_ms,
+            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": achieved / HBM_PEAK_GBS, "algorithmic_bytes_per_launch": alg},
+            "by_lanes": {str(g): v for g, v in per.items()}, "status_counts": status, "steps": steps,
+            "copy_probe": copy_probe}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--lanes", default="8,16,32")
+    ap.add_argument("--scale", type=float, default=1.0)
+    args = ap.parse_args()
+    import paper_1902_04995_amd as rgb
+    from paper_1902_04995_amd import gen3
+    bt = gen3.make_config3("uniform3", seed=0, scale=args.scale)
+    log = lambda s: print(s, file=sys.stderr, flush=True)
+    res = measure(rgb, bt, tuple(int(g) for g in args.lanes.split(",")), args.steps, log)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -31,8 +31,8 @@
 // lanes and reduced with cross-lane shuffles.  Arithmetic is FP64 on FP32
 // inputs: products of two inputs are exact, so the cross products that decide
 // parallel planes and the direction along a line have exact zeros and signs,
-// and for inputs that are small integers every decision is exact.  Each new
-// vertex is recomputed by Cramer's rule from its three planes.
+// and for inputs that are small integers every decision is exact.  A new
+// vertex is the line's point q/|d|^2 moved by the winning bound along d.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -117,14 +117,6 @@ __device__ __forceinline__ bool prefers_up(const V3& c, const V3& d) {
     return d.z < 0.0;
 }
 
-// The point on planes p, q, r (Cramer's rule); det = p.a . (q.a x r.a) != 0.
-__device__ __forceinline__ V3 vertex(const Row& p, const Row& q, const Row& r) {
-    const V3 qr = cross(q.a, r.a), rp = cross(r.a, p.a), pq = cross(p.a, q.a);
-    const double det = dot(p.a, qr);
-    return {(p.b * qr.x + q.b * rp.x + r.b * pq.x) / det, (p.b * qr.y + q.b * rp.y + r.b * pq.y) / det,
-            (p.b * qr.z + q.b * rp.z + r.b * pq.z) / det};
-}
-
 __device__ __forceinline__ bool finite4(float a, float b, float c, float d) {
     return __builtin_isfinite(a) && __builtin_isfinite(b) && __builtin_isfinite(c) && __builtin_isfinite(d);
 }
@@ -144,37 +136,72 @@ __device__ __forceinline__ bool parallel_holds(const Row& Ri, const Row& H) {
     return aik > 0.0 ? lhs <= rhs : lhs >= rhs;
 }
 
-// Row broadcast from lane `src` of the wave.
-__device__ __forceinline__ Row shfl_row(const Row& r, int src) {
-    return {{__shfl(r.a.x, src), __shfl(r.a.y, src), __shfl(r.a.z, src)}, __shfl(r.b, src)};
+// Cross-lane moves within aligned groups: quad_perm xor 1 and xor 2, row
+// half-mirror (8), row mirror (16) as DPP; the swizzle swap of 16 (32) and
+// the other half of the wave (64).  A double moves as its two 32-bit halves.
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int v) {
+    return __builtin_amdgcn_mov_dpp(v, CTRL, 0xF, 0xF, true);
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)dpp_i<CTRL>((int)(uint32_t)u);
+    const uint32_t hi = (uint32_t)dpp_i<CTRL>((int)(uint32_t)(u >> 32));
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ double swz16_d(double v) {
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_ds_swizzle((int)(uint32_t)u, 0x401F);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_ds_swizzle((int)(uint32_t)(u >> 32), 0x401F);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ int imin_(int a, int b) { return a < b ? a : b; }
+
+// Smallest / largest value over the group (every lane gets it), and the
+// smallest int; bounds are never NaN for finite rows (a NaN from an invalid
+// row is dropped, and such an LP is reported INVALID).
+template <int LG>
+__device__ __forceinline__ double group_min_d(double v) {
+    if (LG >= 1) v = __builtin_fmin(v, dpp_d<0xB1>(v));
+    if (LG >= 2) v = __builtin_fmin(v, dpp_d<0x4E>(v));
+    if (LG >= 3) v = __builtin_fmin(v, dpp_d<0x141>(v));
+    if (LG >= 4) v = __builtin_fmin(v, dpp_d<0x140>(v));
+    if (LG >= 5) v = __builtin_fmin(v, swz16_d(v));
+    if (LG >= 6) v = __builtin_fmin(v, __shfl_xor(v, 32));
+    return v;
+}
+template <int LG>
+__device__ __forceinline__ double group_max_d(double v) {
+    if (LG >= 1) v = __builtin_fmax(v, dpp_d<0xB1>(v));
+    if (LG >= 2) v = __builtin_fmax(v, dpp_d<0x4E>(v));
+    if (LG >= 3) v = __builtin_fmax(v, dpp_d<0x141>(v));
+    if (LG >= 4) v = __builtin_fmax(v, dpp_d<0x140>(v));
+    if (LG >= 5) v = __builtin_fmax(v, swz16_d(v));
+    if (LG >= 6) v = __builtin_fmax(v, __shfl_xor(v, 32));
+    return v;
+}
+template <int LG>
+__device__ __forceinline__ int group_min_i(int v) {
+    if (LG >= 1) v = imin_(v, dpp_i<0xB1>(v));
+    if (LG >= 2) v = imin_(v, dpp_i<0x4E>(v));
+    if (LG >= 3) v = imin_(v, dpp_i<0x141>(v));
+    if (LG >= 4) v = imin_(v, dpp_i<0x140>(v));
+    if (LG >= 5) v = imin_(v, __builtin_amdgcn_ds_swizzle(v, 0x401F));
+    if (LG >= 6) v = imin_(v, __shfl_xor(v, 32));
+    return v;
 }
 
-// (value, index) reductions over aligned groups of G lanes: the smallest
-// (largest) value, ties to the smallest index.
-template <int G>
-__device__ __forceinline__ void group_argmin(double& t, int& idx) {
-#pragma unroll
-    for (int off = 1; off < G; off <<= 1) {
-        const double t2 = __shfl_xor(t, off);
-        const int i2 = __shfl_xor(idx, off);
-        if (t2 < t || (t2 == t && i2 < idx)) {
-            t = t2;
-            idx = i2;
-        }
-    }
+// A caller row as its four FP32 inputs (broadcast as floats: half the
+// cross-lane traffic of doubles).
+struct Row4 {
+    float x, y, z, b;
+};
+__device__ __forceinline__ Row to_row(const Row4& f) { return {{(double)f.x, (double)f.y, (double)f.z}, (double)f.b}; }
+__device__ __forceinline__ Row4 shfl_row4(const Row4& f, int src) {
+    return {__shfl(f.x, src), __shfl(f.y, src), __shfl(f.z, src), __shfl(f.b, src)};
 }
-template <int G>
-__device__ __forceinline__ void group_argmax(double& t, int& idx) {
-#pragma unroll
-    for (int off = 1; off < G; off <<= 1) {
-        const double t2 = __shfl_xor(t, off);
-        const int i2 = __shfl_xor(idx, off);
-        if (t2 > t || (t2 == t && i2 < idx)) {
-            t = t2;
-            idx = i2;
-        }
-    }
-}
+__device__ __forceinline__ Row4 load_row4(const Problem3& P, int64_t g) { return {P.ax[g], P.ay[g], P.az[g], P.b[g]}; }
 
 struct State3 {
     V3 x;
@@ -255,15 +282,11 @@ __device__ void solve3_group(const Problem3& P, int64_t lp) {
         // 3D scan window: rows cur .. cur+G-1 against the vertex x
         const int j = cur + gl;
         const bool in = !done && j < mt;
-        Row R = {{0.0, 0.0, 0.0}, 0.0};
-        bool fin = true;
-        if (in) {
-            const int64_t g = start + (j - kBox);
-            const float fx = P.ax[g], fy = P.ay[g], fz = P.az[g], fb = P.b[g];
-            fin = finite4(fx, fy, fz, fb);
-            R = {{(double)fx, (double)fy, (double)fz}, (double)fb};
-        }
+        Row4 F = {0.0f, 0.0f, 0.0f, 0.0f};
+        if (in) F = load_row4(P, start + (j - kBox));
+        const bool fin = finite4(F.x, F.y, F.z, F.b);
         bad |= in && !fin;
+        const Row R = to_row(F);
         const bool viol = in && fin && dot(R.a, st.x) > R.b;
         const uint64_t bal = __ballot(viol) & gmask;
         if (bal == 0) {
@@ -276,7 +299,7 @@ __device__ void solve3_group(const Problem3& P, int64_t lp) {
         // plane i: the first violated row of this group's window
         const int src = __builtin_ctzll(bal);
         const int i = cur + (src - gbase);
-        const Row Ri = shfl_row(R, src);
+        const Row Ri = to_row(shfl_row4(F, src));
         if (is_zero(Ri.a)) {  // 0 <= b with b < 0
             st.dead = true;
             st.status = kInfeasible;
@@ -293,8 +316,9 @@ __device__ void solve3_group(const Problem3& P, int64_t lp) {
                     // 2D scan window on plane i: rows cur2 .. against y
                     const int h = cur2 + gl;
                     const bool in2 = h < i;
-                    Row Rh = {{0.0, 0.0, 0.0}, 0.0};
-                    if (in2) Rh = row_at(P, start, h, s);
+                    Row4 Fh = {0.0f, 0.0f, 0.0f, 0.0f};
+                    if (in2 && h >= kBox) Fh = load_row4(P, start + (h - kBox));
+                    const Row Rh = h >= kBox ? to_row(Fh) : row_at(P, start, h, s);
                     const bool viol2 = in2 && dot(Rh.a, y) > Rh.b;
                     const uint64_t bal2 = __ballot(viol2) & gmask;
                     if (bal2 == 0) {
@@ -303,7 +327,9 @@ __device__ void solve3_group(const Problem3& P, int64_t lp) {
                     }
                     const int src2 = __builtin_ctzll(bal2);
                     const int hv = cur2 + (src2 - gbase);
-                    const Row H = shfl_row(Rh, src2);
+                    // box rows are recomputed, caller rows broadcast as floats
+                    const Row4 Fb = shfl_row4(Fh, src2);
+                    const Row H = hv >= kBox ? to_row(Fb) : row_at(P, start, hv, s);
                     // line L = plane i ^ plane hv: points q/dd + t d
                     const V3 d = cross(Ri.a, H.a);
                     if (is_zero(d)) {
@@ -347,8 +373,12 @@ __device__ void solve3_group(const Problem3& P, int64_t lp) {
                             par |= ng < 0.0;  // parallel to L and excludes it
                         }
                     }
-                    group_argmin<G>(hi, ih);
-                    group_argmax<G>(lo, il);
+                    // group bounds, then the smallest row index attaining each
+                    const double ghi = group_min_d<LG>(hi), glo = group_max_d<LG>(lo);
+                    ih = group_min_i<LG>(hi == ghi ? ih : kNoIdx);
+                    il = group_min_i<LG>(lo == glo ? il : kNoIdx);
+                    hi = ghi;
+                    lo = glo;
                     par = (__ballot(par) & gmask) != 0;
                     const bool up = prefers_up(c, d);
                     const int gb = up ? ih : il;
@@ -362,8 +392,9 @@ __device__ void solve3_group(const Problem3& P, int64_t lp) {
                         st.status = kInvalid;
                         break;
                     }
-                    const Row Gb = row_at(P, start, gb, s);
-                    y = vertex(Ri, H, Gb);
+                    // the vertex q/dd + (tau/dd) d, tau = n_gb/s_gb
+                    const double tau = up ? hi : lo, inv = 1.0 / dd;
+                    y = {fma(tau, d.x, q.x) * inv, fma(tau, d.y, q.y) * inv, fma(tau, d.z, q.z) * inv};
                     f1 = hv;
                     f2 = gb;
                     cur2 = hv + 1;

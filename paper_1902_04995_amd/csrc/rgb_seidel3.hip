@@ -72,8 +72,10 @@ struct V3 {
 };
 
 __device__ __forceinline__ double dot(const V3& a, const V3& b) { return fma(a.x, b.x, fma(a.y, b.y, a.z * b.z)); }
+// For two rows of FP32 inputs every product is exact in FP64, so each
+// component is rounded once (zero exactly when the rows are parallel).
 __device__ __forceinline__ V3 cross(const V3& a, const V3& b) {
-    return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+    return {fma(a.y, b.z, -(a.z * b.y)), fma(a.z, b.x, -(a.x * b.z)), fma(a.x, b.y, -(a.y * b.x))};
 }
 __device__ __forceinline__ bool is_zero(const V3& a) { return a.x == 0.0 && a.y == 0.0 && a.z == 0.0; }
 
@@ -349,9 +351,12 @@ __device__ void solve3_group(const Problem3& P, int64_t lp) {
                     const V3 q = {Ri.b * u.x - H.b * w.x, Ri.b * u.y - H.b * w.y, Ri.b * u.z - H.b * w.z};
                     // 1D LP over rows 0 .. hv-1: row g bounds t by
                     // n_g / (dd s_g) with s_g = a_g.d, n_g = dd b_g - a_g.q;
-                    // the positive factor dd is left out of the comparison key
+                    // the positive factor dd is left out of the comparison key.
+                    // Only the side the objective climbs towards needs its
+                    // row; the other side only needs its extreme value.
+                    const bool up = prefers_up(c, d);
                     double hi = __builtin_huge_val(), lo = -__builtin_huge_val();
-                    int ih = kNoIdx, il = kNoIdx;
+                    int ib = kNoIdx;
                     bool par = false;
                     for (int g = gl; g < hv; g += G) {
                         const Row Rg = row_at(P, start, g, s);
@@ -361,28 +366,27 @@ __device__ void solve3_group(const Problem3& P, int64_t lp) {
                             const double tau = ng / sg;
                             if (tau < hi) {
                                 hi = tau;
-                                ih = g;
+                                if (up) ib = g;
                             }
                         } else if (sg < 0.0) {
                             const double tau = ng / sg;
                             if (tau > lo) {
                                 lo = tau;
-                                il = g;
+                                if (!up) ib = g;
                             }
                         } else {
                             par |= ng < 0.0;  // parallel to L and excludes it
                         }
                     }
-                    // group bounds, then the smallest row index attaining each
-                    const double ghi = group_min_d<LG>(hi), glo = group_max_d<LG>(lo);
-                    ih = group_min_i<LG>(hi == ghi ? ih : kNoIdx);
-                    il = group_min_i<LG>(lo == glo ? il : kNoIdx);
-                    hi = ghi;
-                    lo = glo;
-                    par = (__ballot(par) & gmask) != 0;
-                    const bool up = prefers_up(c, d);
-                    const int gb = up ? ih : il;
-                    if (par || lo > hi) {
+                    // the preferred bound as a minimum over the group (the
+                    // left side negated), the smallest row index attaining it,
+                    // and infeasibility: a bound of the other side crosses it
+                    const double key = up ? hi : -lo;
+                    const double kmin = group_min_d<LG>(key);
+                    const int gb = group_min_i<LG>(key == kmin ? ib : kNoIdx);
+                    const double tau = up ? kmin : -kmin;
+                    const bool crosses = up ? lo > tau : hi < tau;
+                    if ((__ballot(par || crosses) & gmask) != 0) {
                         st.dead = true;
                         st.status = kInfeasible;
                         break;
@@ -393,7 +397,7 @@ __device__ void solve3_group(const Problem3& P, int64_t lp) {
                         break;
                     }
                     // the vertex q/dd + (tau/dd) d, tau = n_gb/s_gb
-                    const double tau = up ? hi : lo, inv = 1.0 / dd;
+                    const double inv = 1.0 / dd;
                     y = {fma(tau, d.x, q.x) * inv, fma(tau, d.y, q.y) * inv, fma(tau, d.z, q.z) * inv};
                     f1 = hv;
                     f2 = gb;

@@ -440,8 +440,10 @@ __device__ void solve3_group(const Problem3& P, int64_t lp) {
     }
 }
 
+// Five waves per SIMD (at most 96 VGPRs, a few dwords spilled on the rare
+// paths) hide more of the dependent FP64 chains than four at 102 VGPRs.
 template <int G>
-__global__ __launch_bounds__(256) void k_seidel3(Problem3 P) {
+__global__ __launch_bounds__(256, 5) void k_seidel3(Problem3 P) {
     constexpr int LG = G == 4 ? 2 : G == 8 ? 3 : G == 16 ? 4 : G == 32 ? 5 : 6;
     const int64_t q = (int64_t)blockIdx.x * (256 / G) + threadIdx.x / G;
     solve3_group<LG>(P, q < P.num_lps ? q : -1);

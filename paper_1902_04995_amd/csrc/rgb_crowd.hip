@@ -172,7 +172,6 @@ __global__ __launch_bounds__(64 * kWaves) void k_crowd_build(const float* px, co
                                                              float* bb) {
     __shared__ uint64_t cand_all[kWaves][kCand];
     __shared__ uint64_t key_all[kWaves][kSlots];
-    __shared__ float row_all[kWaves][3][kSlots];
     const int w = threadIdx.x >> 6;
     const int lane = __lane_id();
     const int64_t i = (int64_t)blockIdx.x * kWaves + w;
@@ -259,42 +258,56 @@ __global__ __launch_bounds__(64 * kWaves) void k_crowd_build(const float* px, co
     }
     if (!ready) nc = keep_best(cand, nc, ki);  // sorted; nc == ki (the batch has more than ki agents)
 
-    // rows: neighbours, then the speed disc; keys put them in random order
+    // rows: neighbours, then the speed disc; keys put them in random order.
+    // A lane builds rows t = lane and t = lane + 64 in registers.  The keys
+    // are distinct (their low 7 bits are t), so row t goes to position
+    // rank(t) = #{s < m : key_s < key_t} of the ascending order: every lane
+    // counts it over the m keys, each read once from LDS as a broadcast (no
+    // dependent chain of sort stages), and stores its rows there directly.
     const int64_t step = step_host >= 0 ? step_host : *step_dev;
     const int m = ki + n_disc;
-    float* rx = row_all[w][0];
-    float* ry = row_all[w][1];
-    float* rb = row_all[w][2];
     uint64_t* key = key_all[w];
-    for (int t = lane; t < kSlots; t += 64) {
-        uint64_t kt = kNone;
+    float rx[2] = {0.0f, 0.0f}, ry[2] = {0.0f, 0.0f}, rb[2] = {0.0f, 0.0f};
+    uint64_t kt[2] = {kNone, kNone};
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int t = lane + 64 * h;
         if (t < nc) {
             const int j = (int)(uint32_t)cand[t];
             const float ddx = px[j] - pxi, ddy = py[j] - pyi;
             const float dist = sqrtf(ddx * ddx + ddy * ddy);
             const bool zero = dist == 0.0f;
-            rx[t] = zero ? 1.0f : ddx / dist;
-            ry[t] = zero ? 0.0f : ddy / dist;
-            rb[t] = 0.5f * (dist - radius);
+            rx[h] = zero ? 1.0f : ddx / dist;
+            ry[h] = zero ? 0.0f : ddy / dist;
+            rb[h] = 0.5f * (dist - radius);
         } else if (t >= ki && t < m) {
-            rx[t] = disc[2 * (t - ki)];
-            ry[t] = disc[2 * (t - ki) + 1];
-            rb[t] = disc[2 * n_disc];
+            rx[h] = disc[2 * (t - ki)];
+            ry[h] = disc[2 * (t - ki) + 1];
+            rb[h] = disc[2 * n_disc];
         }
         if (t < m) {
             const uint64_t ctr = ((uint64_t)step << 40) + ((uint64_t)i << 8) + (uint64_t)t;
-            kt = (splitmix_nth(seed, ctr + 1) & ~uint64_t(127)) | (uint64_t)t;
+            kt[h] = (splitmix_nth(seed, ctr + 1) & ~uint64_t(127)) | (uint64_t)t;
         }
-        key[t] = kt;
+        key[t] = kt[h];
     }
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
-    wave_sort(key, kSlots);
+    int rank0 = 0, rank1 = 0;
+    for (int s = 0; s < m; ++s) {
+        const uint64_t ks = key[s];
+        rank0 += ks < kt[0];
+        rank1 += ks < kt[1];
+    }
     const int64_t o = offsets[i];
-    for (int t = lane; t < m; t += 64) {
-        const int src = (int)(key[t] & 127);
-        ax[o + t] = rx[src];
-        ay[o + t] = ry[src];
-        bb[o + t] = rb[src];
+    if (lane < m) {
+        ax[o + rank0] = rx[0];
+        ay[o + rank0] = ry[0];
+        bb[o + rank0] = rb[0];
+    }
+    if (lane + 64 < m) {
+        ax[o + rank1] = rx[1];
+        ay[o + rank1] = ry[1];
+        bb[o + rank1] = rb[1];
     }
 }
 

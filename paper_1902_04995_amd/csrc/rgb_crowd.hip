@@ -153,10 +153,28 @@ __device__ __forceinline__ int pow2_ceil(int n) {
     return p;
 }
 
-// Keep the `keep` smallest of the first n keys (sorted, at the front).
+// Keep the `keep` smallest of the first n keys (distinct), sorted, at the
+// front.  Up to 128 keys: every lane holds two and counts how many keys are
+// smaller (broadcast LDS reads, no chain of sort stages), then writes each
+// kept key to its rank; beyond that, a bitonic sort.
 __device__ __forceinline__ int keep_best(uint64_t* s, int n, int keep) {
+    const int lane = __lane_id();
+    if (n <= 128) {
+        const uint64_t k0 = lane < n ? s[lane] : kNone, k1 = lane + 64 < n ? s[lane + 64] : kNone;
+        int r0 = 0, r1 = 0;
+        for (int t = 0; t < n; ++t) {
+            const uint64_t v = s[t];
+            r0 += v < k0;
+            r1 += v < k1;
+        }
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        if (lane < n && r0 < keep) s[r0] = k0;
+        if (lane + 64 < n && r1 < keep) s[r1] = k1;
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        return n < keep ? n : keep;
+    }
     const int len = pow2_ceil(n);
-    for (int t = n + __lane_id(); t < len; t += 64) s[t] = kNone;
+    for (int t = n + lane; t < len; t += 64) s[t] = kNone;
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
     wave_sort(s, len);
     return n < keep ? n : keep;

@@ -129,54 +129,35 @@ __device__ __forceinline__ uint64_t splitmix_nth(uint64_t seed, uint64_t n) {
     return z ^ (z >> 31);
 }
 
-// Sort the first `len` (a power of two, <= 256) keys of a wave's LDS array,
-// ascending.  Bitonic network; a wave runs in lock step and LDS executes its
-// accesses in order, so no barrier is needed between stages.
-__device__ __forceinline__ void wave_sort(uint64_t* s, int len) {
-    const int lane = __lane_id();
-    for (int k = 2; k <= len; k <<= 1)
-        for (int j = k >> 1; j > 0; j >>= 1)
-            for (int p = lane; p < (len >> 1); p += 64) {
-                const int a = (p / j) * 2 * j + (p % j), b = a + j;
-                const uint64_t x = s[a], y = s[b];
-                if ((x > y) == ((a & k) == 0)) {
-                    s[a] = y;
-                    s[b] = x;
-                }
-                __atomic_signal_fence(__ATOMIC_SEQ_CST);
-            }
-}
-
-__device__ __forceinline__ int pow2_ceil(int n) {
-    int p = 2;
-    while (p < n) p <<= 1;
-    return p;
-}
-
 // Keep the `keep` smallest of the first n keys (distinct), sorted, at the
-// front.  Up to 128 keys: every lane holds two and counts how many keys are
-// smaller (broadcast LDS reads, no chain of sort stages), then writes each
-// kept key to its rank; beyond that, a bitonic sort.
-__device__ __forceinline__ int keep_best(uint64_t* s, int n, int keep) {
+// front: every lane holds H of them (H = 2 up to 128 keys, 4 up to 256) and
+// counts how many keys are smaller (broadcast LDS reads, no chain of sort
+// stages), then writes each kept key to its rank.
+template <int H>
+__device__ __forceinline__ void keep_by_rank(uint64_t* s, int n, int keep) {
     const int lane = __lane_id();
-    if (n <= 128) {
-        const uint64_t k0 = lane < n ? s[lane] : kNone, k1 = lane + 64 < n ? s[lane + 64] : kNone;
-        int r0 = 0, r1 = 0;
-        for (int t = 0; t < n; ++t) {
-            const uint64_t v = s[t];
-            r0 += v < k0;
-            r1 += v < k1;
-        }
-        __atomic_signal_fence(__ATOMIC_SEQ_CST);
-        if (lane < n && r0 < keep) s[r0] = k0;
-        if (lane + 64 < n && r1 < keep) s[r1] = k1;
-        __atomic_signal_fence(__ATOMIC_SEQ_CST);
-        return n < keep ? n : keep;
+    uint64_t k[H];
+    int r[H];
+#pragma unroll
+    for (int h = 0; h < H; ++h) {
+        k[h] = lane + 64 * h < n ? s[lane + 64 * h] : kNone;
+        r[h] = 0;
     }
-    const int len = pow2_ceil(n);
-    for (int t = n + lane; t < len; t += 64) s[t] = kNone;
+    for (int t = 0; t < n; ++t) {
+        const uint64_t v = s[t];
+#pragma unroll
+        for (int h = 0; h < H; ++h) r[h] += v < k[h];
+    }
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
-    wave_sort(s, len);
+#pragma unroll
+    for (int h = 0; h < H; ++h)
+        if (lane + 64 * h < n && r[h] < keep) s[r[h]] = k[h];
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+__device__ __forceinline__ int keep_best(uint64_t* s, int n, int keep) {
+    if (n <= 128) keep_by_rank<2>(s, n, keep);
+    else keep_by_rank<4>(s, n, keep);
     return n < keep ? n : keep;
 }
 

@@ -160,27 +160,25 @@ __device__ __forceinline__ double swz16_d(double v) {
 }
 __device__ __forceinline__ int imin_(int a, int b) { return a < b ? a : b; }
 
-// Smallest / largest value over the group (every lane gets it), and the
-// smallest int; bounds are never NaN for finite rows (a NaN from an invalid
-// row is dropped, and such an LP is reported INVALID).
+// IEEE minNum as one instruction: the operands are results of arithmetic
+// or copies of them (never signalling NaNs), so the quieting the compiler
+// adds around fmin is not needed; a quiet NaN operand (from an invalid row,
+// whose LP is reported INVALID) is dropped.
+__device__ __forceinline__ double vmin_d(double a, double b) {
+    double r;
+    asm("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+
+// Smallest value over the group (every lane gets it), and the smallest int.
 template <int LG>
 __device__ __forceinline__ double group_min_d(double v) {
-    if (LG >= 1) v = __builtin_fmin(v, dpp_d<0xB1>(v));
-    if (LG >= 2) v = __builtin_fmin(v, dpp_d<0x4E>(v));
-    if (LG >= 3) v = __builtin_fmin(v, dpp_d<0x141>(v));
-    if (LG >= 4) v = __builtin_fmin(v, dpp_d<0x140>(v));
-    if (LG >= 5) v = __builtin_fmin(v, swz16_d(v));
-    if (LG >= 6) v = __builtin_fmin(v, __shfl_xor(v, 32));
-    return v;
-}
-template <int LG>
-__device__ __forceinline__ double group_max_d(double v) {
-    if (LG >= 1) v = __builtin_fmax(v, dpp_d<0xB1>(v));
-    if (LG >= 2) v = __builtin_fmax(v, dpp_d<0x4E>(v));
-    if (LG >= 3) v = __builtin_fmax(v, dpp_d<0x141>(v));
-    if (LG >= 4) v = __builtin_fmax(v, dpp_d<0x140>(v));
-    if (LG >= 5) v = __builtin_fmax(v, swz16_d(v));
-    if (LG >= 6) v = __builtin_fmax(v, __shfl_xor(v, 32));
+    if (LG >= 1) v = vmin_d(v, dpp_d<0xB1>(v));
+    if (LG >= 2) v = vmin_d(v, dpp_d<0x4E>(v));
+    if (LG >= 3) v = vmin_d(v, dpp_d<0x141>(v));
+    if (LG >= 4) v = vmin_d(v, dpp_d<0x140>(v));
+    if (LG >= 5) v = vmin_d(v, swz16_d(v));
+    if (LG >= 6) v = vmin_d(v, __shfl_xor(v, 32));
     return v;
 }
 template <int LG>
@@ -346,9 +344,11 @@ __device__ void solve3_group(const Problem3& P, int64_t lp) {
                         st.status = kInfeasible;
                         break;
                     }
+                    // q = b_i (a_hv x d) - b_hv (a_i x d) = (b_i a_hv - b_hv a_i) x d
                     const double dd = dot(d, d);
-                    const V3 u = cross(H.a, d), w = cross(Ri.a, d);
-                    const V3 q = {Ri.b * u.x - H.b * w.x, Ri.b * u.y - H.b * w.y, Ri.b * u.z - H.b * w.z};
+                    const V3 e = {fma(Ri.b, H.a.x, -(H.b * Ri.a.x)), fma(Ri.b, H.a.y, -(H.b * Ri.a.y)),
+                                  fma(Ri.b, H.a.z, -(H.b * Ri.a.z))};
+                    const V3 q = cross(e, d);
                     // 1D LP over rows 0 .. hv-1: row g bounds t by
                     // n_g / (dd s_g) with s_g = a_g.d, n_g = dd b_g - a_g.q;
                     // the positive factor dd is left out of the comparison key.

@@ -225,7 +225,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(json.dumps({"error": f"--gpus {args.gpus}: this build measures one GPU only; "
+        print(json.dumps({"error": f"--gpus {args.gpus}: the benchmark measures one GPU only; "
                                    "LPs are independent, so N GPUs would each solve their own LP range"}))
         sys.exit(2)
 

@@ -166,3 +166,36 @@ def test_seidel3_full_size_sampled(rgb, oracle_lib):
     st2, x2 = _run(rgb, bt)
     assert np.array_equal(st2, st) and np.array_equal(x2.view(np.int32), x.view(np.int32))
     torch.cuda.empty_cache()
+
+
+def test_seidel3_one_huge_lp(rgb):
+    """One LP of 200,000 planes tangent to the unit sphere (Fibonacci lattice,
+    random row order) among small ones: checked by properties that hold at
+    any size -- every row satisfied, a KKT certificate on the tight rows, and
+    the circumscribed-sphere band |c| <= c.x <= |c| / cos(r) (r the lattice's
+    covering radius, bounded generously)."""
+    import math
+    n = 200_000
+    i = np.arange(n) + 0.5
+    phi = np.arccos(1 - 2 * i / n)
+    th = math.pi * (1 + 5 ** 0.5) * i
+    nrm = np.stack([np.cos(th) * np.sin(phi), np.sin(th) * np.sin(phi), np.cos(phi)], 1)
+    perm = np.random.default_rng(30).permutation(n)
+    nrm = nrm[perm].astype(np.float32)
+    c = np.array([0.3, -0.5, 0.8], np.float32)
+    big = gen3.Batch3(np.array([0, n], np.int64), nrm[:, 0].copy(), nrm[:, 1].copy(), nrm[:, 2].copy(),
+                      np.ones(n, np.float32), c[:1], c[1:2], c[2:], np.zeros(1, np.int8), 1e4)
+    bt = gen3.concat3([gen3.uniform3_batch(3000, 20, seed=31), big, gen3.uniform3_batch(2000, 9, seed=32)])
+    k = 3000
+    for g in (16, 64):
+        st, x = _run(rgb, bt, g)
+        assert st[k] == OPTIMAL, (g, st[k])
+        xk = x[k].astype(np.float64)
+        A = nrm.astype(np.float64)
+        b = np.ones(n)
+        viol, resid = lpcheck.kkt_residual3(A, b, c.astype(np.float64), xk, tight_tol=2e-6)
+        assert viol <= 2e-6 and resid <= 1e-3, (g, viol, resid)
+        cn = float(np.linalg.norm(c.astype(np.float64)))
+        cosr = math.cos(2.0 * math.sqrt(math.pi / n))
+        val = float(c.astype(np.float64) @ xk)
+        assert cn * (1 - 1e-6) <= val <= cn / cosr * (1 + 1e-6), (val, cn)

@@ -777,8 +777,11 @@ __device__ __forceinline__ void load_header(QueueHeader& Qs, const Workspace& W)
 // XCD's waves (workgroups are spread over the XCDs round-robin) mostly hit
 // their own counter.  A wave whose part is drained takes from the others,
 // `chunk` sub-batches per pop.  Every wave exits once all parts are drained.
+// Seven waves per SIMD (at most 72 VGPRs, nothing spilled): more waves hide
+// more of the scan's latency; the grid follows the occupancy the runtime
+// reports.
 template <bool WIDE>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_persist(Problem P, Workspace W,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) void k_persist(Problem P, Workspace W,
                                                                                          PersistPlan plan) {
     __shared__ QueueHeader Qs;
     load_header(Qs, W);
@@ -807,9 +810,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k
 
 // Binned, non-persistent: one wave per sub-batch in queue order (largest LPs
 // first); the grid is an upper bound and surplus waves exit at once.  The
-// hardware dispatcher starts a new wave wherever one finishes.
+// hardware dispatcher starts a new wave wherever one finishes.  Eight waves
+// per SIMD (at most 64 VGPRs, nothing spilled).
 template <bool WIDE>
-__global__ __launch_bounds__(256) void k_binned(Problem P, Workspace W) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_binned(Problem P, Workspace W) {
     __shared__ QueueHeader Qs;
     load_header(Qs, W);
     const int k = (int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));

@@ -189,14 +189,19 @@ def test_one_huge_lp(rgb, oracle_lib):
             assert np.array_equal(a, b_, equal_nan=True)
 
 
-@pytest.mark.parametrize("variant", ["persistent", "pooled"])
-@pytest.mark.parametrize("name", ["uniform", "uneven", "crowd"])
-def test_full_size_sampled(rgb, oracle_lib, name, variant):
-    """Full-size workloads in the launches the benchmark times, checked on a
-    sample of LPs the oracle solves one by one."""
+# the launches the benchmark's autotuner picks for each workload (batched at
+# 16 lanes on uniform, 8 on crowd, binned on uneven), and the other families
+FULL = [("uniform", "batched", 16), ("crowd", "batched", 8), ("uneven", "binned", 0)] + \
+    [(n, v, 0) for n in ("uniform", "uneven", "crowd") for v in ("persistent", "pooled")]
+
+
+@pytest.mark.parametrize("name,variant,g", FULL)
+def test_full_size_sampled(rgb, oracle_lib, name, variant, g):
+    """Full-size workloads in the benchmark's launch configurations, checked
+    on a sample of LPs the oracle solves one by one."""
     bt = gen.make_config(name, seed=0)
-    _say(f"[gpu] case=full {name} variant={variant} lps={bt.num_lps} rows={bt.num_constraints}")
-    got = _run(rgb, bt, variant)
+    _say(f"[gpu] case=full {name} variant={variant} lanes={g} lps={bt.num_lps} rows={bt.num_constraints}")
+    got = _run(rgb, bt, variant, g)
     rng = np.random.default_rng(1)
     idx = np.sort(rng.choice(bt.num_lps, size=min(4000, bt.num_lps), replace=False))
     sub = bt.subset(idx)

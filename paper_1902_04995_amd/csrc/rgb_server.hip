@@ -7,6 +7,16 @@
 // next to each other in the rings and the LP cap and the arena's largest free
 // block allow, copies the rings' spans straight into one arena block, solves
 // it with rgb_solve_batch and copies the results back.
+//
+// Both copies are kernels on the slot's stream that read and write the
+// pinned buffers directly, not DMA-engine copies: the copies, the solve and
+// the completion event then sit in one in-order queue.  With DMA copies the
+// polled event (and a stream synchronisation) sometimes reported completion
+// before the results had landed in pinned memory -- a request read back
+// zeros -- once the process had many streams sharing the hardware queues.
+// The pinned buffers are fine-grained (coherent) host memory, so the GPU
+// reads a reused ring span as the host last wrote it and its result stores
+// are visible to the host when the kernel has finished.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -32,6 +42,21 @@ namespace {
 using Clock = std::chrono::steady_clock;
 
 enum ReqState { kQueued = 0, kAdmitted = 1, kDone = 2, kFailed = 3 };
+
+// Copy n 32-bit words; either side may be host-mapped pinned memory.
+__global__ void k_copy_words(uint32_t* __restrict__ dst, const uint32_t* __restrict__ src, int64_t n) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = src[i];
+}
+
+bool copy_words(void* dst, const void* src, size_t bytes, hipStream_t st) {
+    const int64_t n = (int64_t)(bytes / 4);
+    if (n == 0) return true;
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 2048);
+    hipLaunchKernelGGL(k_copy_words, dim3((unsigned)blocks), dim3(256), 0, st, static_cast<uint32_t*>(dst),
+                       static_cast<const uint32_t*>(src), n);
+    return hipGetLastError() == hipSuccess;
+}
 
 struct Request {
     uint64_t id = 0;
@@ -72,8 +97,9 @@ struct Layout {
 struct Slot {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
-    char* pinned = nullptr;  // offsets: 8 (cap + 1) bytes, then the outputs
-    size_t out_at = 0;       // where the outputs start in `pinned`
+    char* pinned = nullptr;      // offsets: 8 (cap + 1) bytes, then the outputs
+    char* pinned_dev = nullptr;  // the same buffer as the device sees it
+    size_t out_at = 0;           // where the outputs start in `pinned`
     bool busy = false;
     uint64_t arena_off = 0;
     int64_t B = 0, N = 0;
@@ -92,6 +118,7 @@ struct rgb_server {
     // pinned request rings: rows (ax, ay, b) and LPs (cx, cy, end offset of
     // each LP relative to its request)
     char* ring_mem = nullptr;
+    char* ring_dev = nullptr;  // ring_mem as the device sees it
     float *r_ax = nullptr, *r_ay = nullptr, *r_b = nullptr, *r_cx = nullptr, *r_cy = nullptr;
     int64_t* r_end = nullptr;
     rgb::Ring rows, lps;
@@ -195,8 +222,14 @@ bool rgb_server::launch(Slot& s) {
         }
         const Request* f = s.reqs.front();
         char* d = arena_mem + off;
+        // host pointer -> the same bytes as the device sees them
+        auto dev_of = [&](const void* host) -> const void* {
+            const char* h = static_cast<const char*>(host);
+            if (h >= s.pinned && h < s.pinned + s.out_at) return s.pinned_dev + (h - s.pinned);
+            return ring_dev + (h - ring_mem);
+        };
         auto h2d = [&](size_t at, const void* src, size_t bytes) {
-            if (ok && bytes) ok = hipMemcpyAsync(d + at, src, bytes, hipMemcpyHostToDevice, s.stream) == hipSuccess;
+            if (ok && bytes) ok = copy_words(d + at, dev_of(src), bytes, s.stream);
         };
         h2d(L.offsets, offs, 8 * (size_t)(B + 1));
         h2d(L.cx, r_cx + f->lp_pos, 4 * (size_t)B);
@@ -214,9 +247,7 @@ bool rgb_server::launch(Slot& s) {
                                  reinterpret_cast<float*>(d + L.y), reinterpret_cast<int32_t*>(d + L.st), &so,
                                  s.stream) == RGB_OK;
         }
-        if (ok)
-            ok = hipMemcpyAsync(s.pinned + s.out_at, d + L.x, L.total - L.x, hipMemcpyDeviceToHost, s.stream) ==
-                 hipSuccess;
+        if (ok) ok = copy_words(s.pinned_dev + s.out_at, d + L.x, L.total - L.x, s.stream);
         if (ok) ok = hipEventRecord(s.done, s.stream) == hipSuccess;
     }
     s.arena_off = off;
@@ -314,11 +345,15 @@ rgb_err_t rgb_server_create(rgb_ctx_t* ctx, const rgb_server_opts_t* opts, rgb_s
     // a quarter for LPs (16 B each)
     const size_t ring_bytes = (size_t)o.host_ring_mib << 20;
     const int64_t n_rows = (int64_t)(ring_bytes / 4 * 3 / 12), n_lps = (int64_t)(ring_bytes / 4 / 16);
-    if (hipHostMalloc((void**)&s->ring_mem, (size_t)n_rows * 12 + (size_t)n_lps * 16, hipHostMallocDefault) !=
-        hipSuccess) {
+    if (hipHostMalloc((void**)&s->ring_mem, (size_t)n_rows * 12 + (size_t)n_lps * 16,
+                      hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
         s->ring_mem = nullptr;
         rgb_server_destroy(s);
         return RGB_ERR_OOM;
+    }
+    if (hipHostGetDevicePointer((void**)&s->ring_dev, s->ring_mem, 0) != hipSuccess) {
+        rgb_server_destroy(s);
+        return RGB_ERR_DEVICE;
     }
     s->r_end = reinterpret_cast<int64_t*>(s->ring_mem);
     s->r_cx = reinterpret_cast<float*>(s->r_end + n_lps);
@@ -334,9 +369,13 @@ rgb_err_t rgb_server_create(rgb_ctx_t* ctx, const rgb_server_opts_t* opts, rgb_s
         sl.out_at = Layout::al(8 * (cap + 1));
         if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
             hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess ||
-            hipHostMalloc((void**)&sl.pinned, sl.out_at + 3 * Layout::al(4 * cap), hipHostMallocDefault) !=
-                hipSuccess) {
+            hipHostMalloc((void**)&sl.pinned, sl.out_at + 3 * Layout::al(4 * cap),
+                          hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
             sl.pinned = nullptr;
+            rgb_server_destroy(s);
+            return RGB_ERR_DEVICE;
+        }
+        if (hipHostGetDevicePointer((void**)&sl.pinned_dev, sl.pinned, 0) != hipSuccess) {
             rgb_server_destroy(s);
             return RGB_ERR_DEVICE;
         }

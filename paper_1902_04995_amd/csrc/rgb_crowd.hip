@@ -156,7 +156,8 @@ __device__ __forceinline__ void keep_by_rank(uint64_t* s, int n, int keep) {
 }
 
 __device__ __forceinline__ int keep_best(uint64_t* s, int n, int keep) {
-    if (n <= 128) keep_by_rank<2>(s, n, keep);
+    if (n <= 64) keep_by_rank<1>(s, n, keep);
+    else if (n <= 128) keep_by_rank<2>(s, n, keep);
     else keep_by_rank<4>(s, n, keep);
     return n < keep ? n : keep;
 }
@@ -292,10 +293,14 @@ __global__ __launch_bounds__(64 * kWaves) void k_crowd_build(const float* px, co
     }
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
     int rank0 = 0, rank1 = 0;
-    for (int s = 0; s < m; ++s) {
-        const uint64_t ks = key[s];
-        rank0 += ks < kt[0];
-        rank1 += ks < kt[1];
+    if (m <= 64) {  // one key per lane (most agents): half the compares
+        for (int s = 0; s < m; ++s) rank0 += key[s] < kt[0];
+    } else {
+        for (int s = 0; s < m; ++s) {
+            const uint64_t ks = key[s];
+            rank0 += ks < kt[0];
+            rank1 += ks < kt[1];
+        }
     }
     const int64_t o = offsets[i];
     if (lane < m) {

@@ -50,6 +50,7 @@ __global__ void k_copy_words(uint32_t* __restrict__ dst, const uint32_t* __restr
 }
 
 bool copy_words(void* dst, const void* src, size_t bytes, hipStream_t st) {
+    if (bytes % 4 != 0) return false;  // every region of a Layout is a whole number of 16-byte lines
     const int64_t n = (int64_t)(bytes / 4);
     if (n == 0) return true;
     const int64_t blocks = std::min<int64_t>((n + 255) / 256, 2048);

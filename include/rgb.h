@@ -360,7 +360,7 @@ rgb_err_t rgb_reduce_bench_run(int32_t method, int32_t contention, int64_t n, co
  * NaN); UNBOUNDED when the optimum lies on a face of the box (the LP without
  * the box is unbounded, or its optimum lies outside the box), with x the
  * optimum inside the box; INVALID (x NaN) for non-finite rows or objective
- * and offsets that are out of range, decreasing or span 2^30 rows or more.
+ * and offsets that are out of range, decreasing or span more than 2^30 rows.
  * Arithmetic is FP64 on the FP32 inputs.
  *
  * lanes_per_lp: 0 (= 16) or 4, 8, 16, 32, 64 lanes per LP.  ev_begin,

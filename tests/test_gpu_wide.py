@@ -1,7 +1,8 @@
 """GPU: a batch of more than 2^30 rows, which takes the kernels' 64-bit row
 indexing (every other test stays below it).  The batch is generated in device
 memory (~13 GB); all kernel families must agree bit for bit, and a sample of
-LPs is checked against the oracle."""
+LPs is checked against the oracle.  The same rows then hold one LP of more
+than 2^30 rows, which every family must report INVALID without reading it."""
 import sys
 
 import numpy as np
@@ -53,3 +54,18 @@ def test_more_than_2_30_rows(oracle_lib):
     bs, bx = lpcheck.compare(st, x.astype(np.float64), y.astype(np.float64), ref["status"], ref["x"], ref["y"])
     assert len(bs) == 0 and len(bx) == 0, (len(bs), len(bx))
     assert np.all(st == 0)  # every LP contains the unit disk and has 256 spread normals
+    # one LP of 2^30 + 1 rows (over the per-LP limit): INVALID in every family,
+    # its rows never read; the LP after it (the next 100 rows) still solved
+    big = (1 << 30) + 1
+    offs2 = torch.tensor([0, big, big + 100], dtype=torch.int64, device="cuda")
+    sub2 = gen.host_subset(offs2, ax, ay, b, cx[:2], cy[:2], np.array([1]))
+    ref2 = oracle_lib.solve(sub2)
+    for variant, g in (("plain", 0), ("batched", 32), ("persistent", 0), ("binned", 0), ("pooled", 8)):
+        _say(f"[gpu] case=over_limit variant={variant} G={g}")
+        x, y, st = rgb.solve_batch(offs2, ax, ay, b, cx[:2], cy[:2], variant=variant, lanes_per_lp=g)
+        torch.cuda.synchronize()
+        st, x, y = st.cpu().numpy(), x.cpu().numpy(), y.cpu().numpy()
+        assert st[0] == lpcheck.INVALID and np.isnan(x[0]) and np.isnan(y[0]), variant
+        bs, bx = lpcheck.compare(st[1:], x[1:].astype(np.float64), y[1:].astype(np.float64),
+                                 ref2["status"], ref2["x"], ref2["y"])
+        assert len(bs) == 0 and len(bx) == 0, variant

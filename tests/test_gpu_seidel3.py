@@ -199,3 +199,35 @@ def test_seidel3_one_huge_lp(rgb):
         cosr = math.cos(2.0 * math.sqrt(math.pi / n))
         val = float(c.astype(np.float64) @ xk)
         assert cn * (1 - 1e-6) <= val <= cn / cosr * (1 + 1e-6), (val, cn)
+
+
+def test_seidel3_lp_over_row_limit(rgb, oracle_lib):
+    """One LP of 2^30 + 1 planes (over the per-LP limit, ~17 GB of real rows in
+    device memory) is INVALID and never read; the 100-plane LP after it is
+    still solved, at two lane widths."""
+    import torch
+    big = (1 << 30) + 1
+    n = big + 100
+    free, _ = torch.cuda.mem_get_info()
+    if free < 16 * n + (2 << 30):
+        pytest.skip(f"needs {16 * n / 2**30:.1f} GiB of free device memory, {free / 2**30:.1f} free")
+    small = gen3.uniform3_batch(1, 100, seed=33, infeasible_frac=0.0, unbounded_frac=0.0)
+    _say(f"[seidel3] case=over_limit rows={n}")
+    cols = []
+    for a in (small.ax, small.ay, small.az, small.b):
+        t = torch.zeros(n, dtype=torch.float32, device="cuda")
+        t[big:] = torch.from_numpy(a).cuda()
+        cols.append(t)
+    offs = torch.tensor([0, big, n], dtype=torch.int64, device="cuda")
+    c = [torch.from_numpy(np.concatenate([[0.3], v]).astype(np.float32)).cuda() for v in (small.cx, small.cy, small.cz)]
+    ref = oracle_lib.solve3(small)
+    for g in (16, 64):
+        x, y, z, st = rgb.solve3_batch(offs, *cols, *c, small.box, lanes_per_lp=g)
+        torch.cuda.synchronize()
+        st = st.cpu().numpy()
+        xyz = np.stack([x.cpu().numpy(), y.cpu().numpy(), z.cpu().numpy()], 1)
+        assert st[0] == INVALID and np.isnan(xyz[0]).all(), g
+        bs, bx = _mismatches(ref, st[1:], xyz[1:])
+        assert len(bs) + len(bx) == 0, (g, st[1], xyz[1], ref["status"], ref["x"])
+    del cols
+    torch.cuda.empty_cache()

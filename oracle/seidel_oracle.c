@@ -39,11 +39,17 @@
  * of two FP32 values are exact in FP64, hence D_h, det and c.u have exact
  * signs; for small integer inputs every decision here is exact.
  *
+ * Range.  The solver under test computes in FP32, and the paper leaves the
+ * precision open.  Reading taken: an LP whose incremental path visits a
+ * vertex with a coordinate that rounds to an infinite FP32 value is INVALID
+ * (outside the FP32 range), whatever the vertices that follow.
+ *
  * Besides x* and status the oracle reports the defining pair, the number of
  * 1D LPs solved, and a margin: the smallest relative gap
- * |lhs - rhs| / (|lhs| + |rhs|) over the decisions it took (violation tests,
- * parallel tests, u_left vs u_right).  A margin near FP32 epsilon flags an LP
- * whose outcome FP32 arithmetic may not reproduce.
+ * |lhs - rhs| / (|lhs| + |rhs|) over the decisions it took (violation tests of
+ * a vertex or of a ray along a parallel row, parallel rows in a 1D LP,
+ * u_left vs u_right), +inf when no such decision was taken.  A margin near
+ * FP32 epsilon flags an LP whose path FP32 arithmetic may not reproduce.
  */
 #include <math.h>
 #include <stdint.h>
@@ -200,6 +206,14 @@ static lp_result solve_one(int64_t m, const float *ax, const float *ay, const fl
             Y = aix * bh - ahx * bi;
             W = aix * ahy - aiy * ahx;
             if (W < 0.0) { X = -X; Y = -Y; W = -W; }
+            /* a vertex whose coordinates round to an infinite FP32 value lies
+               outside what an FP32 solver can represent: the LP is INVALID */
+            if (isinf((float)(X / W)) || isinf((float)(Y / W))) {
+                res.status = ST_INVALID;
+                res.def_i = (int32_t)i;
+                res.def_j = (int32_t)h;
+                return res;
+            }
         }
     }
 

@@ -284,3 +284,129 @@ def test_pins_catch_planted_mistakes(oracle_lib, mi):
             assert caught, MUTANTS[mi]
         finally:
             oracle_lib._lib = saved
+
+
+# ---------------------------------------------------------------------------
+# margin: the smallest relative gap over the oracle's decisions
+# ---------------------------------------------------------------------------
+def _margin_lps(delta):
+    """Two hand-solved LPs whose decision gaps are known in closed form.
+
+    A (c = (1, 1)): rows x <= 1, y <= 1, x + y <= 2 + delta.  The corner ray
+    violates row 0 (a ray along x = 1 follows), then row 1 (vertex (1, 1));
+    row 2 is tested at that vertex: lhs 2, rhs 2 + delta, so the only gap is
+    delta / (4 + delta), and x* = (1, 1).
+
+    B (c = (0, 1)): rows y <= 1, -x <= 0, x - y <= -1 - delta.  Rows 0 and 1
+    lead to the vertex (0, 1); row 2 is violated there with gap
+    delta / (2 + delta); on its line (direction (1, 1), |a|^2 = 2) row 0 is a
+    right bound N/D = (1 - delta)/1 and row 1 a left bound N/D = -(1+delta)/-1,
+    so u_left > u_right with gap relgap(-(1 + delta), -(1 - delta)) = delta:
+    INFEASIBLE, margin delta / (2 + delta).
+
+    C (c = (0, 1)): rows y <= x, y <= -x, -x - (3/2 - delta) y <= 1/2,
+    y <= -1.  Rows 0 and 1 give the vertex (0, 0) (scaled W = 2); row 2 holds
+    there (gap relgap(0, 1) = 1) and row 3 is violated (gap 1).  On y = -1
+    (direction (-1, 0)), in positions t = -x: right bounds t <= 1 (row 0) and t <= -1 + delta (row 2), left
+    bound t >= -1 (row 1): feasible, and the one small gap is
+    relgap(1 * 1, (-1 + delta) * (-1)) = delta / (2 - delta).  c is orthogonal
+    to the line, so the smaller x wins: t = -1 + delta, x* = (1 - delta, -1)."""
+    a = _single([1, 0, 1], [0, 1, 1], [1, 1, 2 + delta], 1.0, 1.0)
+    b = _single([0, -1, 1], [1, 0, -1], [1, 0, -1 - delta], 0.0, 1.0)
+    c = _single([-1, 1, -1, 0], [1, 1, -(1.5 - delta), 1], [0, 0, 0.5, -1], 0.0, 1.0)
+    return gen.concat([a, b, c])
+
+
+@pytest.mark.parametrize("delta", [2.0 ** -20, 2.0 ** -12, 0.5])
+def test_oracle_margin_closed_form(oracle_lib, delta):
+    res = oracle_lib.solve(_margin_lps(delta), threads=1)
+    assert res["status"].tolist() == [OPTIMAL, INFEASIBLE, OPTIMAL]
+    assert (res["x"][0], res["y"][0]) == (1.0, 1.0)
+    assert (res["x"][2], res["y"][2]) == (1.0 - delta, -1.0)
+    assert res["margin"][0] == pytest.approx(delta / (4 + delta), rel=1e-12)
+    assert res["margin"][1] == pytest.approx(delta / (2 + delta), rel=1e-12)
+    assert res["margin"][2] == pytest.approx(delta / (2 - delta), rel=1e-12)
+    assert res["n_1dlp"].tolist() == [2, 3, 3]
+
+
+def test_oracle_margin_near_tie_vs_generic(oracle_lib):
+    """A planted near tie sits below 1e-6; an LP with O(1) gaps above 1e-3;
+    an LP that decides nothing by comparison (only the corner and one ray)
+    reports +inf."""
+    tie = _margin_lps(2.0 ** -21)
+    wide = _margin_lps(0.5)
+    res_t = oracle_lib.solve(tie, threads=1)
+    res_w = oracle_lib.solve(wide, threads=1)
+    assert np.all(res_t["margin"] < 1e-6)
+    assert np.all(res_w["margin"] > 1e-3)
+    res = oracle_lib.solve(_single([1.0], [0.0], [1.0], 1.0, 1.0), threads=1)  # one row: corner, then a ray
+    assert res["status"][0] == UNBOUNDED and res["margin"][0] == np.inf
+
+
+def test_oracle_margin_scale_invariant(oracle_lib):
+    """Every gap is a ratio of two quantities that scale alike with b, so
+    b -> 2^k b leaves the margin bit for bit."""
+    bt = gen.tiny_random_batch(600, m_max=30, seed=19)
+    base = oracle_lib.solve(bt, threads=2)
+    r = oracle_lib.solve(_perturbed(bt, b=(bt.b * np.float32(2.0 ** 7)).astype(np.float32)), threads=2)
+    assert np.array_equal(r["margin"], base["margin"])
+    assert np.all(base["margin"] >= 0)
+
+
+# ---------------------------------------------------------------------------
+# FP32 range: a visited vertex FP32 cannot hold makes the LP INVALID
+# ---------------------------------------------------------------------------
+def test_oracle_fp32_range_rule(oracle_lib):
+    big = np.float32(3.0e38)
+    # x <= 3e38, y <= 1: the vertex (3e38, 1) is representable
+    r = oracle_lib.solve(_single([1, 0], [0, 1], [big, 1], 1.0, 1.0), threads=1)
+    assert r["status"][0] == OPTIMAL and r["x"][0] == float(big)
+    # 1e-10 x <= 1e30 puts the vertex at x = 1e40, beyond FP32
+    a, b = np.float32(1e-10), np.float32(1e30)
+    r = oracle_lib.solve(_single([a, 0], [0, 1], [b, 1], 1.0, 1.0), threads=1)
+    assert r["status"][0] == INVALID
+    # the same vertex on the way, then x <= 5: still INVALID (the path visits it)
+    r = oracle_lib.solve(_single([a, 0, 1], [0, 1, 0], [b, 1, 5], 1.0, 1.0), threads=1)
+    assert r["status"][0] == INVALID
+    # with x <= 5 first, the far row never makes a vertex: OPTIMAL at (5, 1)
+    r = oracle_lib.solve(_single([1, a, 0], [0, 0, 1], [5, b, 1], 1.0, 1.0), threads=1)
+    assert r["status"][0] == OPTIMAL and (r["x"][0], r["y"][0]) == (5.0, 1.0)
+
+
+MARGIN_MUTANTS = [
+    ("    return fabs(lhs - rhs) / den;", "    return fabs(lhs - rhs);"),   # gap not relative
+    ("            violated = lhs > rhs;\n            lower_margin(&res.margin, relgap(lhs, rhs));\n        }\n        if",
+     "            violated = lhs > rhs;\n        }\n        if"),                    # vertex tests dropped
+    ("            lower_margin(&res.margin, relgap(lhs, rhs));\n            if (lhs < rhs) {",
+     "            if (lhs < rhs) {"),                                               # u_left/u_right gap dropped
+    ("if (isinf((float)(X / W)) || isinf((float)(Y / W))) {", "if (0) {"),         # range rule dropped
+]
+
+
+@pytest.mark.parametrize("mi", range(len(MARGIN_MUTANTS)))
+def test_margin_and_range_pins_catch_planted_mistakes(oracle_lib, mi):
+    import ctypes
+    src = open(os.path.join(os.path.dirname(oracle_lib.__file__), "seidel_oracle.c")).read()
+    old, new = MARGIN_MUTANTS[mi]
+    assert src.count(old) == 1, old
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "m.c")
+        so = os.path.join(d, "m.so")
+        open(c, "w").write(src.replace(old, new))
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fPIC", "-shared", "-o", so, c, "-lm"])
+        lib = ctypes.CDLL(so)
+        saved = oracle_lib._lib
+        lib.rgb_oracle_solve_range.argtypes = saved.rgb_oracle_solve_range.argtypes
+        oracle_lib._lib = lib
+        try:
+            failed = 0
+            for test in (lambda: test_oracle_margin_closed_form(oracle_lib, 2.0 ** -12),
+                         lambda: test_oracle_margin_closed_form(oracle_lib, 0.5),
+                         lambda: test_oracle_fp32_range_rule(oracle_lib)):
+                try:
+                    test()
+                except AssertionError:
+                    failed += 1
+            assert failed > 0, MARGIN_MUTANTS[mi]
+        finally:
+            oracle_lib._lib = saved

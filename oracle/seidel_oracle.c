@@ -45,11 +45,13 @@
  * (outside the FP32 range), whatever the vertices that follow.
  *
  * Besides x* and status the oracle reports the defining pair, the number of
- * 1D LPs solved, and a margin: the smallest relative gap
- * |lhs - rhs| / (|lhs| + |rhs|) over the decisions it took (violation tests of
- * a vertex or of a ray along a parallel row, parallel rows in a 1D LP,
- * u_left vs u_right), +inf when no such decision was taken.  A margin near
- * FP32 epsilon flags an LP whose path FP32 arithmetic may not reproduce.
+ * 1D LPs solved, and a margin: the smallest relative gap over the decisions it
+ * took (violation tests of a vertex or of a ray along a parallel row,
+ * parallel rows in a 1D LP, u_left vs u_right), +inf when no such decision
+ * was taken.  Each gap is |lhs - rhs| over the sum of the magnitudes of the
+ * terms both sides add up (for a vertex test |a_x X| + |a_y Y| + |b W|), the
+ * scale of their rounding.  A margin near FP32 epsilon flags an LP whose
+ * path FP32 arithmetic may not reproduce.
  */
 #include <math.h>
 #include <stdint.h>
@@ -64,10 +66,12 @@
 #define K_RAY 1    /* RAY along line l in direction dir * u_l */
 #define K_POINT 2  /* vertex of lines l and h */
 
-static double relgap(double lhs, double rhs) {
-    double den = fabs(lhs) + fabs(rhs);
-    if (den == 0.0) return 0.0;
-    return fabs(lhs - rhs) / den;
+/* Gap of a decision lhs > rhs (or <) relative to the magnitudes of the terms
+   the two sides are sums of: the rounding noise of a sum scales with them,
+   not with the sum, which may cancel. */
+static double relgap(double lhs, double rhs, double scale) {
+    if (scale == 0.0) return 0.0;
+    return fabs(lhs - rhs) / scale;
 }
 
 static void lower_margin(double *margin, double g) {
@@ -138,13 +142,14 @@ static lp_result solve_one(int64_t m, const float *ax, const float *ay, const fl
                 double lhs = bl * (aix * alx + aiy * aly);
                 double rhs = bi * (alx * alx + aly * aly);
                 violated = lhs > rhs;
-                lower_margin(&res.margin, relgap(lhs, rhs));
+                lower_margin(&res.margin,
+                             relgap(lhs, rhs, fabs(bl) * (fabs(aix * alx) + fabs(aiy * aly)) + fabs(rhs)));
             }
         } else {
             double lhs = aix * X + aiy * Y;
             double rhs = bi * W;
             violated = lhs > rhs;
-            lower_margin(&res.margin, relgap(lhs, rhs));
+            lower_margin(&res.margin, relgap(lhs, rhs, fabs(aix * X) + fabs(aiy * Y) + fabs(rhs)));
         }
         if (!violated) continue;
 
@@ -153,18 +158,20 @@ static lp_result solve_one(int64_t m, const float *ax, const float *ay, const fl
         double nrm2 = aix * aix + aiy * aiy;
         int64_t hi = -1, lo = -1;
         double hiN = 0.0, hiD = 1.0, loN = 0.0, loD = -1.0;
+        double hiS = 0.0, loS = 0.0; /* magnitudes of the terms of hiN, loN */
         for (int64_t j = 0; j < i; ++j) {
             double ajx = ax[j], ajy = ay[j], bj = b[j];
             double D = aix * ajy - aiy * ajx;
             double dotp = aix * ajx + aiy * ajy;
             double N = bj * nrm2 - bi * dotp;
+            double S = fabs(bj * nrm2) + fabs(bi) * (fabs(aix * ajx) + fabs(aiy * ajy));
             if (D > 0.0) {
-                if (hi < 0 || N * hiD < hiN * D) { hi = j; hiN = N; hiD = D; }
+                if (hi < 0 || N * hiD < hiN * D) { hi = j; hiN = N; hiD = D; hiS = S; }
             } else if (D < 0.0) {
-                if (lo < 0 || N * loD > loN * D) { lo = j; loN = N; loD = D; }
+                if (lo < 0 || N * loD > loN * D) { lo = j; loN = N; loD = D; loS = S; }
             } else {
                 /* parallel (or zero normal): line i lies inside h iff N >= 0 */
-                if (ajx != 0.0 || ajy != 0.0) lower_margin(&res.margin, relgap(bj * nrm2, bi * dotp));
+                if (ajx != 0.0 || ajy != 0.0) lower_margin(&res.margin, relgap(bj * nrm2, bi * dotp, S));
                 if (N < 0.0) {
                     res.status = ST_INFEASIBLE;
                     res.def_i = (int32_t)i;
@@ -176,7 +183,7 @@ static lp_result solve_one(int64_t m, const float *ax, const float *ay, const fl
         if (hi >= 0 && lo >= 0) {
             /* u_left > u_right  <=>  loN/loD > hiN/hiD  <=>  loN*hiD < hiN*loD (loD < 0 < hiD) */
             double lhs = loN * hiD, rhs = hiN * loD;
-            lower_margin(&res.margin, relgap(lhs, rhs));
+            lower_margin(&res.margin, relgap(lhs, rhs, loS * hiD - hiS * loD));
             if (lhs < rhs) {
                 res.status = ST_INFEASIBLE;
                 res.def_i = (int32_t)i;

@@ -306,35 +306,46 @@ def _margin_lps(delta):
 
     C (c = (0, 1)): rows y <= x, y <= -x, -x - (3/2 - delta) y <= 1/2,
     y <= -1.  Rows 0 and 1 give the vertex (0, 0) (scaled W = 2); row 2 holds
-    there (gap relgap(0, 1) = 1) and row 3 is violated (gap 1).  On y = -1
-    (direction (-1, 0)), in positions t = -x: right bounds t <= 1 (row 0) and t <= -1 + delta (row 2), left
-    bound t >= -1 (row 1): feasible, and the one small gap is
-    relgap(1 * 1, (-1 + delta) * (-1)) = delta / (2 - delta).  c is orthogonal
-    to the line, so the smaller x wins: t = -1 + delta, x* = (1 - delta, -1)."""
+    there (gap 1) and row 3 is violated (gap 1).  On y = -1 (direction
+    (-1, 0), |a|^2 = 1), in positions t = -x: right bounds t <= 1 (row 0) and
+    t <= -1 + delta (row 2, N = -1 + delta, terms 1/2 + 3/2 - delta), left bound
+    t >= -1 (row 1, N = 1, terms 1): feasible, and the one small gap is
+    |1 * 1 - (-1 + delta)(-1)| / (1 * 1 + (2 - delta) * 1) = delta / (3 - delta).
+    c is orthogonal to the line, so the smaller x wins: t = -1 + delta,
+    x* = (1 - delta, -1).
+
+    D (c = (1, 1)): rows x <= 1e6, y <= 1e6, x - y <= delta.  At the vertex
+    (1e6, 1e6) the last test adds 1e6 - 1e6 = 0 against delta: the gap is
+    delta over the terms' magnitudes 1e6 + 1e6 + delta (the sum itself
+    cancels to 0, which must not make the decision look safe)."""
     a = _single([1, 0, 1], [0, 1, 1], [1, 1, 2 + delta], 1.0, 1.0)
     b = _single([0, -1, 1], [1, 0, -1], [1, 0, -1 - delta], 0.0, 1.0)
     c = _single([-1, 1, -1, 0], [1, 1, -(1.5 - delta), 1], [0, 0, 0.5, -1], 0.0, 1.0)
-    return gen.concat([a, b, c])
+    d = _single([1, 0, 1], [0, 1, -1], [1e6, 1e6, delta], 1.0, 1.0)
+    return gen.concat([a, b, c, d])
 
 
 @pytest.mark.parametrize("delta", [2.0 ** -20, 2.0 ** -12, 0.5])
 def test_oracle_margin_closed_form(oracle_lib, delta):
     res = oracle_lib.solve(_margin_lps(delta), threads=1)
-    assert res["status"].tolist() == [OPTIMAL, INFEASIBLE, OPTIMAL]
+    assert res["status"].tolist() == [OPTIMAL, INFEASIBLE, OPTIMAL, OPTIMAL]
     assert (res["x"][0], res["y"][0]) == (1.0, 1.0)
     assert (res["x"][2], res["y"][2]) == (1.0 - delta, -1.0)
+    assert (res["x"][3], res["y"][3]) == (1e6, 1e6)
     assert res["margin"][0] == pytest.approx(delta / (4 + delta), rel=1e-12)
     assert res["margin"][1] == pytest.approx(delta / (2 + delta), rel=1e-12)
-    assert res["margin"][2] == pytest.approx(delta / (2 - delta), rel=1e-12)
-    assert res["n_1dlp"].tolist() == [2, 3, 3]
+    assert res["margin"][2] == pytest.approx(delta / (3 - delta), rel=1e-12)
+    d32 = float(np.float32(delta))
+    assert res["margin"][3] == pytest.approx(d32 / (2e6 + d32), rel=1e-12)
+    assert res["n_1dlp"].tolist() == [2, 3, 3, 2]
 
 
 def test_oracle_margin_near_tie_vs_generic(oracle_lib):
     """A planted near tie sits below 1e-6; an LP with O(1) gaps above 1e-3;
     an LP that decides nothing by comparison (only the corner and one ray)
     reports +inf."""
-    tie = _margin_lps(2.0 ** -21)
-    wide = _margin_lps(0.5)
+    tie = _margin_lps(2.0 ** -21).subset([0, 1, 2])
+    wide = _margin_lps(0.5).subset([0, 1, 2])
     res_t = oracle_lib.solve(tie, threads=1)
     res_w = oracle_lib.solve(wide, threads=1)
     assert np.all(res_t["margin"] < 1e-6)
@@ -374,11 +385,13 @@ def test_oracle_fp32_range_rule(oracle_lib):
 
 
 MARGIN_MUTANTS = [
-    ("    return fabs(lhs - rhs) / den;", "    return fabs(lhs - rhs);"),   # gap not relative
-    ("            violated = lhs > rhs;\n            lower_margin(&res.margin, relgap(lhs, rhs));\n        }\n        if",
-     "            violated = lhs > rhs;\n        }\n        if"),                    # vertex tests dropped
-    ("            lower_margin(&res.margin, relgap(lhs, rhs));\n            if (lhs < rhs) {",
-     "            if (lhs < rhs) {"),                                               # u_left/u_right gap dropped
+    ("    return fabs(lhs - rhs) / scale;", "    return fabs(lhs - rhs);"),   # gap not relative
+    ("relgap(lhs, rhs, fabs(aix * X) + fabs(aiy * Y) + fabs(rhs))",
+     "relgap(lhs, rhs, fabs(lhs) + fabs(rhs))"),                                # scaled by the sum, not its terms
+    ("            lower_margin(&res.margin, relgap(lhs, rhs, fabs(aix * X) + fabs(aiy * Y) + fabs(rhs)));\n",
+     ""),                                                                        # vertex tests dropped
+    ("            lower_margin(&res.margin, relgap(lhs, rhs, loS * hiD - hiS * loD));\n",
+     ""),                                                                        # u_left/u_right gap dropped
     ("if (isinf((float)(X / W)) || isinf((float)(Y / W))) {", "if (0) {"),         # range rule dropped
 ]
 

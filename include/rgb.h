@@ -18,8 +18,9 @@
  *   RGB_OPTIMAL    x*, y* written
  *   RGB_INFEASIBLE no point satisfies every row (x, y = NaN)
  *   RGB_UNBOUNDED  feasible, no lexicographic optimum (x, y = NaN)
- *   RGB_INVALID    a non-finite ax/ay/b/cx/cy in the LP, or malformed offsets
- *                  for this LP (x, y = NaN)
+ *   RGB_INVALID    a non-finite ax/ay/b/cx/cy in the LP, malformed offsets
+ *                  for this LP, or a vertex on the method's path whose
+ *                  coordinates exceed the FP32 range (x, y = NaN)
  * A row with ax = ay = 0 means 0 <= b: it empties the LP if b < 0 and is
  * ignored otherwise.  An LP with no rows is RGB_UNBOUNDED.
  *
@@ -34,6 +35,12 @@
  * Rows are read only inside [0, num_constraints): an LP whose offsets fall
  * outside, decrease, or span more than 2^30 rows gets RGB_INVALID instead of
  * being read.
+ *
+ * Arithmetic is FP32 on the FP32 inputs, with the decisions that FP32 cannot
+ * settle (a row parallel to a violated line, u_left within rounding of
+ * u_right, a position beyond the FP32 range) taken in FP64; the statuses are
+ * those of a serial FP64 Seidel on the same rows.  Rows are expected to be
+ * scaled so that |b_i| / |a_i| and |a_i|^2 stay inside the FP32 normal range.
  *
  * Errors: calls return rgb_err_t synchronously for argument errors and never
  * throw across the ABI.  Launch failures return RGB_ERR_DEVICE; a fault
@@ -105,7 +112,8 @@ typedef struct {
                                in 1/1024 (the rest are dealt round-robin); -1 = none */
     int32_t* n_1dlp_out;    /* optional device int32[num_lps]: 1D LPs solved per LP */
     void* ev_begin;         /* optional hipEvent_t recorded on the stream right before the solve kernel */
-    void* ev_end;           /* optional hipEvent_t recorded right after it (binning kernels excluded) */
+    void* ev_end;           /* optional hipEvent_t recorded right after it and the FP64 fix-up kernel
+                               that follows every solve (binning kernels excluded) */
 } rgb_solve_opts_t;
 
 /* A launch configuration: kernel family and shape.  rgb_autotune() fills one
@@ -128,10 +136,22 @@ typedef struct {
 /* Version string of the library. */
 const char* rgb_version(void);
 
+/* Options of a context; pass NULL for defaults. */
+typedef struct {
+    const char* tuning_table; /* path of a tuning table written by rgb_autotune (JSON, see there), or
+                                 NULL: the context starts with the entry the table holds for its
+                                 device, if any, as its AUTO configuration; a missing file or a
+                                 table without this device leaves the defaults */
+    int32_t reserved[4];      /* zero */
+} rgb_ctx_opts_t;
+
 /* Create a context on HIP device `device` (the caller's current device is
- * left unchanged).  *out receives the context.  Errors: INVALID_ARG (bad
- * device or NULL out), DEVICE. */
-rgb_err_t rgb_ctx_create(int device, rgb_ctx_t** out);
+ * left unchanged).  *out receives the context.  The table named by
+ * opts->tuning_table is read once, here; the context keeps no reference to
+ * it.  Errors: INVALID_ARG (bad device, NULL out, a table that cannot be
+ * parsed or whose entry for this device is not a valid configuration),
+ * DEVICE. */
+rgb_err_t rgb_ctx_create(int device, const rgb_ctx_opts_t* opts, rgb_ctx_t** out);
 
 /* Free the context and its workspace.  Waits for no stream: the caller
  * synchronises the streams it used first.  NULL is a no-op. */
@@ -158,17 +178,34 @@ rgb_err_t rgb_ctx_get_tuning(const rgb_ctx_t* ctx, rgb_tuning_t* out);
 rgb_err_t rgb_ctx_set_tuning(rgb_ctx_t* ctx, const rgb_tuning_t* tuning);
 
 /* Choose the fastest configuration for this batch by measurement and make
- * it ctx's AUTO configuration.  Arguments as rgb_solve_batch (the outputs
- * are overwritten by the trial solves); the kernel families are compared
- * first, then lanes per LP class by class (classes holding >= 4% of the rows,
- * largest first), then the queue share and chunk of the persistent kernel.
- * Each candidate is timed `reps` times with HIP events on `stream` (the
- * median counts) until `budget_ms` of wall time is spent.  Blocks until done.
- * *best (may be NULL) receives the winner.  Errors as rgb_solve_batch. */
+ * it ctx's AUTO configuration (the paper fixes its block size at compile
+ * time, Sec. 5; here the launch shape is measured on the target).  Arguments
+ * as rgb_solve_batch (the outputs are overwritten by the trial solves); the
+ * kernel families are compared first, then lanes per LP class by class for
+ * the class-aware families (classes holding >= 4% of the rows, largest
+ * first), then the queue share and chunk of the persistent kernel.  Each
+ * candidate is timed `reps` times with HIP events on `stream` (the median
+ * counts) until `budget_ms` of wall time is spent.  Blocks until done.
+ * *best (may be NULL) receives the winner.
+ *
+ * table_path (may be NULL): a tuning table, created if missing, into which
+ * the result is merged; a later rgb_ctx_create with opts->tuning_table =
+ * table_path starts from it without searching.  The table is JSON:
+ *   {"format": "rgb-tuning-1", "devices": {"<device name> <gfx arch> <CUs>cu":
+ *     {"variant": "binned", "batched_lanes": 16, "queue_share": 128, "chunk": 1,
+ *      "grid": 0, "pool_lanes": 4, "pool_wait": 2, "pool_rows": 4, "ms": 1.43,
+ *      "classes": {"13": {"log2_lanes": 6}, ...}}}}
+ * keyed by device and size class (class c holds LPs with 2^(c-1) < m <= 2^c
+ * rows).  The family and scalar knobs are the winner's; "classes" lists the
+ * classes whose lanes per LP this or an earlier run measured (this run's
+ * replace earlier ones; others are kept).  Entries of other devices are
+ * kept.  The file is replaced atomically (written beside it, then renamed).
+ * Errors as rgb_solve_batch, and INVALID_ARG when the table cannot be read
+ * or written. */
 rgb_err_t rgb_autotune(rgb_ctx_t* ctx, int64_t num_lps, int64_t num_constraints, const int64_t* offsets,
                        const float* ax, const float* ay, const float* b, const float* cx, const float* cy,
                        float* x_out, float* y_out, int32_t* status_out, int32_t reps, double budget_ms,
-                       void* stream, rgb_tuning_t* best);
+                       const char* table_path, void* stream, rgb_tuning_t* best);
 
 /* A solve captured once as a HIP graph (binning, queue set-up and the solve
  * kernel) and replayed with rgb_plan_launch: same buffers, same launch

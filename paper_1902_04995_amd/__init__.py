@@ -71,6 +71,10 @@ class Tuning(ctypes.Structure):
         return t
 
 
+class _CtxOpts(ctypes.Structure):
+    _fields_ = [("tuning_table", ctypes.c_char_p), ("reserved", ctypes.c_int32 * 4)]
+
+
 class _CrowdOpts(ctypes.Structure):
     _fields_ = [("radius", ctypes.c_float), ("vmax", ctypes.c_float), ("dt", ctypes.c_float), ("cell", ctypes.c_float),
                 ("n_disc", ctypes.c_int32), ("reserved", ctypes.c_int32), ("seed", ctypes.c_uint64)]
@@ -103,7 +107,7 @@ def lib():
         L = ctypes.CDLL(LIB_PATH)
         P, I64, I32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
         L.rgb_version.restype = ctypes.c_char_p
-        L.rgb_ctx_create.argtypes = [ctypes.c_int, ctypes.POINTER(P)]
+        L.rgb_ctx_create.argtypes = [ctypes.c_int, ctypes.POINTER(_CtxOpts), ctypes.POINTER(P)]
         L.rgb_ctx_create.restype = I32
         L.rgb_ctx_destroy.argtypes = [P]
         L.rgb_ctx_destroy.restype = I32
@@ -115,7 +119,8 @@ def lib():
         L.rgb_ctx_get_tuning.restype = I32
         L.rgb_ctx_set_tuning.argtypes = [P, ctypes.POINTER(Tuning)]
         L.rgb_ctx_set_tuning.restype = I32
-        L.rgb_autotune.argtypes = [P, I64, I64] + [P] * 9 + [I32, ctypes.c_double, P, ctypes.POINTER(Tuning)]
+        L.rgb_autotune.argtypes = [P, I64, I64] + [P] * 9 + [I32, ctypes.c_double, ctypes.c_char_p, P,
+                                                              ctypes.POINTER(Tuning)]
         L.rgb_autotune.restype = I32
         L.rgb_plan_create.argtypes = [P, I64, I64] + [P] * 9 + [ctypes.POINTER(_SolveOpts), ctypes.POINTER(P)]
         L.rgb_plan_create.restype = I32
@@ -156,14 +161,18 @@ def lib():
 
 
 class Context:
-    """Owns an rgb_ctx_t on one device."""
+    """Owns an rgb_ctx_t on one device.  ``tuning_table``: path of a table
+    written by rgb_autotune; its entry for this device becomes the AUTO
+    configuration."""
 
-    def __init__(self, device: int = 0):
+    def __init__(self, device: int = 0, tuning_table: str | None = None):
         L = lib()
         h = ctypes.c_void_p()
-        rc = L.rgb_ctx_create(int(device), ctypes.byref(h))
+        opts = _CtxOpts()
+        opts.tuning_table = os.fsencode(tuning_table) if tuning_table else None
+        rc = L.rgb_ctx_create(int(device), ctypes.byref(opts), ctypes.byref(h))
         if rc != 0:
-            raise RgbError(f"rgb_ctx_create({device}) failed: {rc}")
+            raise RgbError(f"rgb_ctx_create({device}, tuning_table={tuning_table!r}) failed: {rc}")
         self.handle = h
         self.device = int(device)
 
@@ -219,6 +228,18 @@ def _check_tensor(t, name, dtype, device):
         raise ValueError(f"{name} must be contiguous")
 
 
+def _check_out(out, B, device):
+    """Caller-supplied (x, y, status) outputs: float32, float32, int32, on the
+    batch's device, contiguous, B entries each (the kernels write B of each)."""
+    import torch
+    if len(out) != 3:
+        raise ValueError("out must be (x, y, status)")
+    for t, name, dt in zip(out, ("x", "y", "status"), (torch.float32, torch.float32, torch.int32)):
+        _check_tensor(t, f"out {name}", dt, device)
+        if t.numel() != B:
+            raise ValueError(f"out {name} holds {t.numel()} entries, the batch has {B} LPs")
+
+
 def make_opts(variant="auto", lanes_per_lp=0, pool_wait=0, chunk=0, grid=0, n_1dlp=None, events=None,
               queue_share=0, pool_rows=0) -> _SolveOpts:
     o = _SolveOpts()
@@ -243,7 +264,8 @@ def _event_handle(ev):
 
 
 def solve_batch(offsets, ax, ay, b, cx, cy, *, variant="auto", lanes_per_lp=0, pool_wait=0, chunk=0, grid=0,
-                queue_share=0, pool_rows=0, want_n_1dlp=False, out=None, stream=None, ctx: Context | None = None, events=None):
+                queue_share=0, pool_rows=0, want_n_1dlp=False, out=None, stream=None, ctx: Context | None = None,
+                events=None):
     """Solve a CSR-offset SoA batch held in CUDA tensors (offsets int64[B+1];
     ax, ay, b float32[N]; cx, cy float32[B]).  Enqueues on ``stream`` (default:
     torch's current stream) and returns (x, y, status[, n_1dlp]) tensors that
@@ -265,6 +287,7 @@ def solve_batch(offsets, ax, ay, b, cx, cy, *, variant="auto", lanes_per_lp=0, p
         y = torch.empty(B, dtype=torch.float32, device=dev)
         st = torch.empty(B, dtype=torch.int32, device=dev)
     else:
+        _check_out(out, B, dev)
         x, y, st = out
     n1d = torch.empty(B, dtype=torch.int32, device=dev) if want_n_1dlp else None
     ctx = ctx or context(dev.index or 0)
@@ -294,21 +317,25 @@ def _batch_args(offsets, ax, ay, b, cx, cy, out):
     if out is None:
         out = (torch.empty(B, dtype=torch.float32, device=dev), torch.empty(B, dtype=torch.float32, device=dev),
                torch.empty(B, dtype=torch.int32, device=dev))
+    else:
+        _check_out(out, B, dev)
     x, y, st = out
     return dev, B, N, [_ptr(offsets), _ptr(ax), _ptr(ay), _ptr(b), _ptr(cx), _ptr(cy), _ptr(x), _ptr(y), _ptr(st)], out
 
 
 def autotune(offsets, ax, ay, b, cx, cy, *, reps=3, budget_ms=2000.0, out=None, stream=None,
-             ctx: Context | None = None) -> Tuning:
+             ctx: Context | None = None, table_path: str | None = None) -> Tuning:
     """Measure the kernel families and launch shapes on this batch and make the
-    fastest one the context's AUTO configuration (rgb_autotune)."""
+    fastest one the context's AUTO configuration (rgb_autotune); with
+    ``table_path`` the result is merged into that tuning table."""
     import torch
     dev, B, N, args, out = _batch_args(offsets, ax, ay, b, cx, cy, out)
     ctx = ctx or context(dev.index or 0)
     if stream is None:
         stream = torch.cuda.current_stream(dev)
     best = Tuning()
-    rc = lib().rgb_autotune(ctx.handle, B, N, *args, int(reps), float(budget_ms), ctypes.c_void_p(stream.cuda_stream),
+    rc = lib().rgb_autotune(ctx.handle, B, N, *args, int(reps), float(budget_ms),
+                            os.fsencode(table_path) if table_path else None, ctypes.c_void_p(stream.cuda_stream),
                             ctypes.byref(best))
     ctx.check(rc, "rgb_autotune")
     return best
@@ -614,6 +641,11 @@ def solve3_batch(offsets, ax, ay, az, b, cx, cy, cz, box, *, lanes_per_lp=0, out
     if out is None:
         out = tuple(torch.empty(B, dtype=torch.float32, device=dev) for _ in range(3)) + \
             (torch.empty(B, dtype=torch.int32, device=dev),)
+    else:
+        if len(out) != 4:
+            raise ValueError("out must be (x, y, z, status)")
+        _check_out(tuple(out[:2]) + (out[3],), B, dev)
+        _check_out((out[2], out[2], out[3]), B, dev)
     x, y, z, st = out
     ctx = ctx or context(dev.index or 0)
     if stream is None:

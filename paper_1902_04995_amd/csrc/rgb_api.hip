@@ -31,6 +31,7 @@ constexpr int kMaxStreams = 32;
 
 struct rgb_ctx {
     int device = 0;
+    std::string device_key;  // "<name> <arch> <CUs>cu": the tuning table's key
     int num_cus = 0;
     int persist_blocks_per_cu = 1;
     rgb_tuning_t tuning{};
@@ -104,6 +105,37 @@ bool tuning_valid(const rgb_tuning_t& t) {
         if (t.log2_lanes[c] < 2 || t.log2_lanes[c] > 6) return false;
     return lanes_ok(t.batched_lanes) && t.queue_share >= 0 && t.queue_share <= 1024 && t.chunk >= 1 &&
            t.grid >= 0 && rgb::pool_supported(t.pool_lanes, t.pool_rows) && t.pool_wait >= 0 && t.pool_wait <= 8;
+}
+
+rgb::TableEntry table_entry_of(const rgb_tuning_t& t) {
+    rgb::TableEntry e;
+    e.variant = t.variant;
+    for (int c = 0; c < rgb::kClasses; ++c) e.log2_lanes[c] = t.log2_lanes[c];
+    e.batched_lanes = t.batched_lanes;
+    e.queue_share = t.queue_share;
+    e.chunk = t.chunk;
+    e.grid = t.grid;
+    e.pool_lanes = t.pool_lanes;
+    e.pool_wait = t.pool_wait;
+    e.pool_rows = t.pool_rows;
+    e.ms = t.ms;
+    return e;
+}
+
+rgb_tuning_t tuning_of(const rgb::TableEntry& e) {
+    rgb_tuning_t t;
+    std::memset(&t, 0, sizeof(t));
+    t.variant = e.variant;
+    for (int c = 0; c < rgb::kClasses; ++c) t.log2_lanes[c] = e.log2_lanes[c];
+    t.batched_lanes = e.batched_lanes;
+    t.queue_share = e.queue_share;
+    t.chunk = e.chunk;
+    t.grid = e.grid;
+    t.pool_lanes = e.pool_lanes;
+    t.pool_wait = e.pool_wait;
+    t.pool_rows = e.pool_rows;
+    t.ms = (float)e.ms;
+    return t;
 }
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
@@ -239,17 +271,22 @@ rgb_err_t resolve(rgb_ctx_t* ctx, const rgb_solve_opts_t& o, int& variant, rgb_t
 rgb_err_t enqueue(rgb_ctx_t* ctx, const rgb::Problem& P, int variant, const rgb_tuning_t& cfg,
                   const rgb::Workspace* W, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
     hipError_t e;
+    // every family is followed by the FP64 fix-up of the LPs it deferred;
+    // the events bracket both
     if (variant == RGB_VARIANT_PLAIN) {
         if (ev0) (void)hipEventRecord(ev0, st);
         e = rgb::launch_plain(P, st);
+        if (e == hipSuccess) e = rgb::launch_fixup(P, st);
         if (ev1) (void)hipEventRecord(ev1, st);
     } else if (variant == RGB_VARIANT_BATCHED) {
         if (ev0) (void)hipEventRecord(ev0, st);
         e = rgb::launch_group(P, cfg.batched_lanes, st);
+        if (e == hipSuccess) e = rgb::launch_fixup(P, st);
         if (ev1) (void)hipEventRecord(ev1, st);
     } else if (variant == RGB_VARIANT_POOLED) {
         if (ev0) (void)hipEventRecord(ev0, st);
         e = rgb::launch_pool(P, cfg.pool_lanes, cfg.pool_rows, cfg.pool_wait, st);
+        if (e == hipSuccess) e = rgb::launch_fixup(P, st);
         if (ev1) (void)hipEventRecord(ev1, st);
     } else {
         rgb::PersistPlan plan{};
@@ -272,7 +309,7 @@ extern "C" {
 
 const char* rgb_version(void) { return "rgb-mi355x 0.2 (gfx950)"; }
 
-rgb_err_t rgb_ctx_create(int device, rgb_ctx_t** out) {
+rgb_err_t rgb_ctx_create(int device, const rgb_ctx_opts_t* opts, rgb_ctx_t** out) {
     if (!out) return RGB_ERR_INVALID_ARG;
     *out = nullptr;
     int n = 0;
@@ -288,8 +325,21 @@ rgb_err_t rgb_ctx_create(int device, rgb_ctx_t** out) {
         return RGB_ERR_DEVICE;
     }
     ctx->num_cus = prop.multiProcessorCount;
+    std::string arch = prop.gcnArchName;
+    arch = arch.substr(0, arch.find(':'));
+    ctx->device_key = std::string(prop.name) + " " + arch + " " + std::to_string(prop.multiProcessorCount) + "cu";
     ctx->persist_blocks_per_cu = rgb::persist_blocks_per_cu();
     default_tuning(ctx->tuning);
+    if (opts && opts->tuning_table) {
+        rgb::TableEntry e = table_entry_of(ctx->tuning);
+        const int r = rgb::table_load(opts->tuning_table, ctx->device_key, e);
+        rgb_tuning_t t = tuning_of(e);
+        if (r < 0 || (r == 1 && !tuning_valid(t))) {
+            delete ctx;
+            return RGB_ERR_INVALID_ARG;
+        }
+        if (r == 1) ctx->tuning = t;
+    }
     *out = ctx;
     return RGB_OK;
 }
@@ -350,7 +400,7 @@ rgb_err_t rgb_solve_batch(rgb_ctx_t* ctx, int64_t num_lps, int64_t num_constrain
 rgb_err_t rgb_autotune(rgb_ctx_t* ctx, int64_t num_lps, int64_t num_constraints, const int64_t* offsets,
                        const float* ax, const float* ay, const float* b, const float* cx, const float* cy,
                        float* x_out, float* y_out, int32_t* status_out, int32_t reps, double budget_ms,
-                       void* stream, rgb_tuning_t* best) {
+                       const char* table_path, void* stream, rgb_tuning_t* best) {
     if (!ctx) return RGB_ERR_INVALID_ARG;
     ctx->last_error.clear();
     Batch B{num_lps, num_constraints, offsets, ax, ay, b, cx, cy, x_out, y_out, status_out};
@@ -396,6 +446,9 @@ rgb_err_t rgb_autotune(rgb_ctx_t* ctx, int64_t num_lps, int64_t num_constraints,
     };
     rgb_tuning_t win = ctx->tuning;
     win.ms = 1e30f;
+    // best of the class-aware families (persistent, binned) and the classes whose lanes were measured
+    rgb_tuning_t class_best = ctx->tuning;
+    bool class_tuned[rgb::kClasses] = {};
     auto try_cfg = [&](rgb_tuning_t cand) -> rgb_err_t {
         float ms = 0.0f;
         rgb_err_t r = measure(cand, ms);
@@ -460,14 +513,23 @@ rgb_err_t rgb_autotune(rgb_ctx_t* ctx, int64_t num_lps, int64_t num_constraints,
         }
         for (int c : order) {
             if (elapsed_ms() > budget_ms) break;
+            float best_ms = 1e30f;
             for (int v : {RGB_VARIANT_PERSISTENT, RGB_VARIANT_BINNED})
                 for (int lg = 2; lg <= 6; ++lg) {
                     rgb_tuning_t cand = base;
                     cand.variant = v;
                     cand.log2_lanes[c] = lg;
-                    if ((r = try_cfg(cand)) != RGB_OK) return r;
+                    float ms = 0.0f;
+                    if ((r = measure(cand, ms)) != RGB_OK) return r;
+                    cand.ms = ms;
+                    if (ms < win.ms) win = cand;
+                    if (ms < best_ms) {
+                        best_ms = ms;
+                        class_best = cand;
+                    }
                 }
-            if (win.variant == RGB_VARIANT_PERSISTENT || win.variant == RGB_VARIANT_BINNED) base = win;
+            class_tuned[c] = true;
+            base = class_best;
         }
         // 4. queue share and chunk of the persistent kernel
         for (int share : {0, 128, 512, 1024})
@@ -488,6 +550,17 @@ rgb_err_t rgb_autotune(rgb_ctx_t* ctx, int64_t num_lps, int64_t num_constraints,
     if (rc != RGB_OK) return rc;
     ctx->tuning = win;
     if (best) *best = win;
+    if (table_path) {
+        // the family and knobs of the winner; lanes per class from the best
+        // class-aware configuration, for the classes that were measured
+        rgb::TableEntry e = table_entry_of(win);
+        for (int c = 0; c < rgb::kClasses; ++c) {
+            e.log2_lanes[c] = class_best.log2_lanes[c];
+            e.tuned[c] = class_tuned[c];
+        }
+        if (rgb::table_save(table_path, ctx->device_key, e) != 0)
+            return fail(ctx, RGB_ERR_INVALID_ARG, "cannot write the tuning table %s", table_path);
+    }
     return RGB_OK;
 }
 

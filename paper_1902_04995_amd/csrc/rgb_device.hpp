@@ -11,19 +11,25 @@
 // rows (Eq. (3)-(4)): each earlier row is one work unit (Sec. 3) giving a
 // left or right bound on the line.
 //
-// Arithmetic is FP32 with three guards that keep every status decision
-// equal to the exact one:
+// Arithmetic is FP32 with guards that keep every status decision equal to
+// the one a serial FP64 Seidel takes:
 //   * signs of 2x2 determinants of inputs (which side a row bounds, whether
 //     two rows are parallel, the direction c prefers along a line, ray
 //     tests) use Kahan's FMA determinant, whose relative error is below
 //     2 ulps, so the sign and an exact zero are always right;
-//   * the parallel case (Sec. 2.1: the row either leaves the line whole or
-//     empties it) and parallel ray tests are decided in FP64, where
+//   * a 1D LP is first run fast: every row's position along the line in
+//     FP32, min/max, and a running sum of the positions that turns
+//     non-finite when a row is parallel to the line or a position
+//     overflows; then a careful FP32 rerun decides parallel rows in FP64
+//     (Sec. 2.1: the row either leaves the line whole or empties it), where
 //     products of FP32 inputs are exact;
 //   * when u_left and u_right (Eq. (3)-(4)) are within FP32 noise of each
-//     other, infeasibility is re-decided in FP64 from the two bounding rows.
+//     other, infeasibility is decided in FP64 from the two rows that attain
+//     them; when a position overflows FP32, the whole 1D LP is decided by an
+//     FP64 pass that compares bounds by cross-multiplication.
 // x* is recomputed at the end by Cramer's rule from the defining pair, with
-// Kahan determinants (a few ulps per component).
+// Kahan determinants (a few ulps per component).  A vertex beyond the FP32
+// range makes the LP INVALID.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -35,6 +41,9 @@ constexpr int kOptimal = 0;
 constexpr int kInfeasible = 1;
 constexpr int kUnbounded = 2;
 constexpr int kInvalid = 3;
+// Internal status of an LP that a fast kernel left to the FP64 fix-up pass
+// (an FP32 overflow in one of its 1D LPs); never returned.
+constexpr int kDeferred = 4;
 
 constexpr int kCorner = 0;
 constexpr int kRay = 1;
@@ -183,26 +192,29 @@ __device__ __forceinline__ float vmax3(float a, float b, float c) {
 
 // One work unit (Sec. 3) as candidates: the row's position if it bounds from
 // the right (else hi, the neutral value) and if it bounds from the left (else
-// lo).  Rows with D >= 0 count as right bounds, so a parallel row (D = 0)
-// gives sigma = r * (1/0) = +-inf: harmless when +inf (or NaN for r = 0), and
-// -inf when it may empty the line.  hi = -inf therefore flags "look again":
-// the caller reruns the rows with work_unit_exact(), which decides parallel
-// rows in FP64.  A NaN position leaves a bound unchanged, and a tie only picks
-// the sign of a zero bound, which no later test or output depends on.
+// lo).  Rows with D >= 0 count as right bounds; a parallel row (D = 0) gives a
+// position r * (1/0) that is infinite or NaN, whatever the sign of its exact
+// offset.  `chk` sums the positions, so it ends non-finite exactly when some
+// row was parallel to the line or its position overflowed (or the sum did);
+// the caller then reruns the 1D LP with the careful passes below, which
+// decide those rows exactly.  A non-finite candidate never reaches a bound
+// that is used unchecked.
 __device__ __forceinline__ void wu_candidates(float ax, float ay, float b, const Line& L, float hi, float lo,
-                                              float& th, float& tl) {
+                                              float& th, float& tl, float& chk) {
     float D;
     float sig = wu_sigma(ax, ay, b, L, D);
     bool right = D >= 0.0f;
     th = right ? sig : hi;
     tl = right ? lo : sig;
+    chk += sig;
 }
 
 // Fold one row into the bounds on line L: hi = min over right bounds
 // (u_right), lo = max over left bounds (u_left).
-__device__ __forceinline__ void work_unit(float ax, float ay, float b, const Line& L, float& hi, float& lo) {
+__device__ __forceinline__ void work_unit(float ax, float ay, float b, const Line& L, float& hi, float& lo,
+                                          float& chk) {
     float th, tl;
-    wu_candidates(ax, ay, b, L, hi, lo, th, tl);
+    wu_candidates(ax, ay, b, L, hi, lo, th, tl, chk);
     hi = vmin(hi, th);
     lo = vmax(lo, tl);
 }
@@ -210,28 +222,89 @@ __device__ __forceinline__ void work_unit(float ax, float ay, float b, const Lin
 // Four work units folded with v_min3 / v_max3 (the same bounds as four
 // work_unit calls: min and max are exact and order-free).
 __device__ __forceinline__ void work_units4(const float (&x)[4], const float (&y)[4], const float (&c)[4], const Line& L,
-                                            float& hi, float& lo) {
+                                            float& hi, float& lo, float& chk) {
     float th[4], tl[4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) wu_candidates(x[k], y[k], c[k], L, hi, lo, th[k], tl[k]);
+    for (int k = 0; k < 4; ++k) wu_candidates(x[k], y[k], c[k], L, hi, lo, th[k], tl[k], chk);
     hi = vmin3(vmin3(hi, th[0], th[1]), th[2], th[3]);
     lo = vmax3(vmax3(lo, tl[0], tl[1]), tl[2], tl[3]);
 }
 
-// The careful version of work_unit for the rare rerun: parallel rows are
-// left out of the bounds and decided exactly.
-__device__ __forceinline__ void work_unit_exact(float ax, float ay, float b, const Line& L, float& hi, float& lo,
-                                                bool& par_inf) {
-    float D;
-    float sig = wu_sigma(ax, ay, b, L, D);
-    if (D > 0.0f) hi = sig < hi ? sig : hi;
-    else if (D < 0.0f) lo = sig > lo ? sig : lo;
-    else par_inf |= parallel_empties(ax, ay, b, L);
+// Bounds of a fast pass as they are handed on: hi = -inf when `chk` says a
+// row needs the careful rerun (no genuine right bound is -inf).
+__device__ __forceinline__ float flag_rerun(float hi, float chk) {
+    return __builtin_isfinite(chk) ? hi : -__builtin_huge_valf();
 }
 
-// Exact-in-FP64 re-decision of u_left > u_right from the two bounding rows.
-// With D_h = a_l x a_h and N_h = b_h |a_l|^2 - b_l (a_l.a_h), a bound sits at
-// N_h / D_h along u (scaled by |a_l|^2); lo > hi iff N_lo D_hi < N_hi D_lo.
+// The careful FP32 rerun of a flagged 1D LP: parallel rows are left out of
+// the bounds and decided exactly (par); a non-parallel row whose FP32
+// position is not finite sets ovf, and the 1D LP is then decided in FP64.
+__device__ __forceinline__ void work_unit_exact(float ax, float ay, float b, const Line& L, float& hi, float& lo,
+                                                bool& par, bool& ovf) {
+    float D;
+    float sig = wu_sigma(ax, ay, b, L, D);
+    if (D == 0.0f) {
+        par |= parallel_empties(ax, ay, b, L);
+        return;
+    }
+    ovf |= !__builtin_isfinite(sig);
+    if (D > 0.0f) hi = sig < hi ? sig : hi;
+    else lo = sig > lo ? sig : lo;
+}
+
+// The 1D LP of Eq. (3)-(4) in FP64, for the rare case FP32 cannot settle (a
+// position beyond the FP32 range).  With D_h = a_l x a_h and N_h = b_h |a_l|^2 - b_l (a_l.a_h), row h
+// bounds line l at N_h / D_h (times 1/|a_l|^2) from the right if D_h > 0 and
+// from the left if D_h < 0; bounds are compared by cross-multiplication and
+// ties keep the smaller row index, so the decisions are those of a serial
+// FP64 Seidel that evaluates the same expressions.  One side at a time keeps
+// the registers this rare path needs to a few.  Parallel rows are not seen
+// here: any of them makes the fast pass's position sum non-finite, and the
+// careful FP32 rerun has decided them before this pass runs.
+struct Bound64 {
+    double N, D;  // position N / D; I = its row, -1: none on this side
+    int I;
+};
+
+// Fold row h into the best bound of one side (right: the smallest position
+// among D > 0, left: the largest among D < 0).
+template <bool RIGHT>
+__device__ __forceinline__ void exact_row(Bound64& e, float lxf, float lyf, float lbf, float axf, float ayf, float bf,
+                                          int h) {
+    double lx = lxf, ly = lyf, ax = axf, ay = ayf;
+    double D = lx * ay - ly * ax;
+    if (RIGHT ? !(D > 0.0) : !(D < 0.0)) return;
+    double n2 = lx * lx + ly * ly;
+    double dot = lx * ax + ly * ay;
+    double N = (double)bf * n2 - (double)lbf * dot;
+    bool take = e.I < 0 || (RIGHT ? N * e.D < e.N * D : N * e.D > e.N * D);
+    if (take) {
+        e.N = N;
+        e.D = D;
+        e.I = h;
+    }
+}
+
+// Fold another lane's bound o into e (the same rule: strictly better, or
+// equal with a smaller row index).
+template <bool RIGHT>
+__device__ __forceinline__ void exact_merge(Bound64& e, double oN, double oD, int oI) {
+    if (oI < 0) return;
+    double l = oN * e.D, r = e.N * oD;
+    if (e.I < 0 || (RIGHT ? l < r : l > r) || (l == r && oI < e.I)) {
+        e.N = oN;
+        e.D = oD;
+        e.I = oI;
+    }
+}
+
+// u_left > u_right from the two sides' FP64 bounds.
+__device__ __forceinline__ bool exact_empty(const Bound64& hi, const Bound64& lo) {
+    return hi.I >= 0 && lo.I >= 0 && lo.N * hi.D < hi.N * lo.D;
+}
+
+// The same decision from the two rows that attain u_left and u_right (a near
+// tie in FP32): the expressions of exact_row, for those two rows only.
 __device__ __forceinline__ bool exact_lo_gt_hi(const Line& L, float lox, float loy, float lob, float hix,
                                                float hiy, float hib) {
     double lx = L.lx, ly = L.ly, lb = L.lb;
@@ -258,9 +331,11 @@ __device__ __forceinline__ bool prefers_up(const Line& L, float cx, float cy) {
     return L.lx < 0.0f;
 }
 
-// New state after a feasible 1D LP on line L (row v) with bounds (lo, hi).
-__device__ __forceinline__ void move_on_line(LpState& st, int v, const Line& L, float hi, float lo, bool up) {
-    float sig = up ? hi : lo;
+// New state after a feasible 1D LP on line L (row v) whose chosen end sits
+// at position sig along u (+-inf: no bound on that side, a ray).  A vertex
+// whose FP32 coordinates overflow ends the LP as INVALID: its optimum (or a
+// vertex on its way there) lies outside the range FP32 can represent.
+__device__ __forceinline__ void move_to(LpState& st, int v, const Line& L, float sig, bool up) {
     st.l = v;
     st.lx = L.lx;
     st.ly = L.ly;
@@ -279,7 +354,15 @@ __device__ __forceinline__ void move_on_line(LpState& st, int v, const Line& L, 
         st.py = __builtin_fmaf(sig, L.uy, L.p0y);
         st.qx = 0.0f;
         st.qy = 0.0f;
+        if (!__builtin_isfinite(st.px) || !__builtin_isfinite(st.py)) {
+            st.kind = kDead;
+            st.dead_status = kInvalid;
+        }
     }
+}
+
+__device__ __forceinline__ void move_on_line(LpState& st, int v, const Line& L, float hi, float lo, bool up) {
+    move_to(st, v, L, up ? hi : lo, up);
 }
 
 __device__ __forceinline__ void set_dead(LpState& st, int status) {

@@ -5,6 +5,15 @@
 // buffer filled by several host threads), the chunk's offsets rebased to its
 // first row, rgb_solve_batch, results back.  The state (streams, device and
 // pinned buffers) lives in the context and grows on demand.
+//
+// Every copy is a kernel on the chunk's stream that reads or writes the host
+// buffer through its device-visible address (launch_copy), never a DMA-engine
+// copy: the host waits on an event recorded after the results' copy, and a
+// completion marker that follows a kernel on the same in-order queue has
+// covered every store of that kernel.  The served path moved to kernel
+// copies after a completed event that followed DMA copies was observed
+// before the results had reached host memory; this path shares the
+// mechanism.  The staging buffers are fine-grained (coherent) pinned memory.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -48,26 +57,49 @@ struct HostSlot {
     hipEvent_t done = nullptr;
     char* dev = nullptr;
     size_t dev_cap = 0;
-    char* pin = nullptr;
+    char* pin = nullptr;      // fine-grained pinned staging buffer
+    char* pin_dev = nullptr;  // the same buffer as the device sees it
     size_t pin_cap = 0;
     // the chunk in flight on this slot (its results still to be copied out)
     bool busy = false;
     int64_t lp0 = 0, B = 0, N = 0;
 };
 
+__global__ __launch_bounds__(256) void k_copy16(uint4* __restrict__ dst, const uint4* __restrict__ src, int64_t n) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = src[i];
+}
+
+__global__ __launch_bounds__(256) void k_copy4(uint32_t* __restrict__ dst, const uint32_t* __restrict__ src,
+                                               int64_t n) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = src[i];
+}
+
+__global__ __launch_bounds__(256) void k_copy1(uint8_t* __restrict__ dst, const uint8_t* __restrict__ src,
+                                               int64_t n) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = src[i];
+}
+
 __global__ void k_rebase(int64_t* offs, int64_t n, int64_t base) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) offs[i] -= base;
 }
 
-bool is_pinned(const void* p) {
+// Is p pinned host memory?  Then *dev receives the address a kernel uses for
+// it (nullptr stays nullptr).
+bool pinned_dev(const void* p, const char** dev) {
+    *dev = nullptr;
     if (!p) return true;  // nothing to copy
     hipPointerAttribute_t a;
     if (hipPointerGetAttributes(&a, p) != hipSuccess) {
         (void)hipGetLastError();  // pageable memory is reported as an error: clear it
         return false;
     }
-    return a.type == hipMemoryTypeHost;
+    if (a.type != hipMemoryTypeHost || !a.devicePointer) return false;
+    *dev = static_cast<const char*>(a.devicePointer);
+    return true;
 }
 
 // memcpy split over a few host threads for large copies.
@@ -89,6 +121,35 @@ void par_copy(void* dst, const void* src, size_t bytes) {
 }
 
 }  // namespace
+
+bool launch_copy(void* dst, const void* src, size_t bytes, hipStream_t stream) {
+    if (bytes == 0) return true;
+    const uintptr_t a = reinterpret_cast<uintptr_t>(dst) | reinterpret_cast<uintptr_t>(src);
+    int64_t n;
+    int width;
+    if ((a % 16) == 0 && bytes % 16 == 0) {
+        n = (int64_t)(bytes / 16);
+        width = 16;
+    } else if ((a % 4) == 0 && bytes % 4 == 0) {
+        n = (int64_t)(bytes / 4);
+        width = 4;
+    } else {
+        n = (int64_t)bytes;
+        width = 1;
+    }
+    // enough waves in flight for host memory's latency, at most 4096 blocks
+    const unsigned blocks = (unsigned)std::min<int64_t>((n + 255) / 256, 4096);
+    if (width == 16)
+        hipLaunchKernelGGL(k_copy16, dim3(blocks), dim3(256), 0, stream, static_cast<uint4*>(dst),
+                           static_cast<const uint4*>(src), n);
+    else if (width == 4)
+        hipLaunchKernelGGL(k_copy4, dim3(blocks), dim3(256), 0, stream, static_cast<uint32_t*>(dst),
+                           static_cast<const uint32_t*>(src), n);
+    else
+        hipLaunchKernelGGL(k_copy1, dim3(blocks), dim3(256), 0, stream, static_cast<uint8_t*>(dst),
+                           static_cast<const uint8_t*>(src), n);
+    return hipGetLastError() == hipSuccess;
+}
 
 struct HostPath {
     HostSlot slot[kHostStreams];
@@ -150,9 +211,12 @@ extern "C" rgb_err_t rgb_solve_batch_host(rgb_ctx_t* ctx, int64_t num_lps, int64
                 hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess)
                 return RGB_ERR_DEVICE;
     }
-    const bool pin_in = rgb::is_pinned(offsets) && rgb::is_pinned(ax) && rgb::is_pinned(ay) && rgb::is_pinned(b) &&
-                        rgb::is_pinned(cx) && rgb::is_pinned(cy);
-    const bool pin_out = rgb::is_pinned(x_out) && rgb::is_pinned(y_out) && rgb::is_pinned(status_out);
+    // device-visible addresses of the caller's buffers where they are pinned
+    const char *d_off, *d_ax, *d_ay, *d_b, *d_cx, *d_cy, *d_x, *d_y, *d_st;
+    const bool pin_in = rgb::pinned_dev(offsets, &d_off) && rgb::pinned_dev(ax, &d_ax) && rgb::pinned_dev(ay, &d_ay) &&
+                        rgb::pinned_dev(b, &d_b) && rgb::pinned_dev(cx, &d_cx) && rgb::pinned_dev(cy, &d_cy);
+    const bool pin_out =
+        rgb::pinned_dev(x_out, &d_x) && rgb::pinned_dev(y_out, &d_y) && rgb::pinned_dev(status_out, &d_st);
 
     rgb_err_t rc = RGB_OK;
     // results of a finished chunk, from the staging buffer to the caller
@@ -193,37 +257,45 @@ extern "C" rgb_err_t rgb_solve_batch_host(rgb_ctx_t* ctx, int64_t num_lps, int64
         if (need_pin && s.pin_cap < L.total) {
             if (s.pin) (void)hipHostFree(s.pin);
             s.pin = nullptr;
+            s.pin_dev = nullptr;
             s.pin_cap = 0;
-            if (hipHostMalloc((void**)&s.pin, L.total, hipHostMallocDefault) != hipSuccess) {
+            if (hipHostMalloc((void**)&s.pin, L.total, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
+                s.pin = nullptr;
                 rc = RGB_ERR_OOM;
+                break;
+            }
+            if (hipHostGetDevicePointer((void**)&s.pin_dev, s.pin, 0) != hipSuccess) {
+                rc = RGB_ERR_DEVICE;
                 break;
             }
             s.pin_cap = L.total;
         }
-        // inputs: offsets (rebased on the device), objectives, rows
-        const char* src_off = reinterpret_cast<const char*>(offsets + lp0);
-        const char* src_cx = reinterpret_cast<const char*>(cx + lp0);
-        const char* src_cy = reinterpret_cast<const char*>(cy + lp0);
-        const char* src_ax = reinterpret_cast<const char*>(ax + row0);
-        const char* src_ay = reinterpret_cast<const char*>(ay + row0);
-        const char* src_b = reinterpret_cast<const char*>(b + row0);
+        // inputs: offsets (rebased on the device), objectives, rows, read by
+        // copy kernels through the device-visible address of the caller's
+        // pinned buffers or of the staging buffer
+        const char* src_off = d_off + 8 * lp0;
+        const char* src_cx = d_cx + 4 * lp0;
+        const char* src_cy = d_cy + 4 * lp0;
+        const char* src_ax = d_ax + 4 * row0;
+        const char* src_ay = d_ay + 4 * row0;
+        const char* src_b = d_b + 4 * row0;
         if (!pin_in) {
-            rgb::par_copy(s.pin + L.offsets, src_off, 8 * (size_t)(B + 1));
-            rgb::par_copy(s.pin + L.cx, src_cx, 4 * (size_t)B);
-            rgb::par_copy(s.pin + L.cy, src_cy, 4 * (size_t)B);
-            rgb::par_copy(s.pin + L.ax, src_ax, 4 * (size_t)N);
-            rgb::par_copy(s.pin + L.ay, src_ay, 4 * (size_t)N);
-            rgb::par_copy(s.pin + L.b, src_b, 4 * (size_t)N);
-            src_off = s.pin + L.offsets;
-            src_cx = s.pin + L.cx;
-            src_cy = s.pin + L.cy;
-            src_ax = s.pin + L.ax;
-            src_ay = s.pin + L.ay;
-            src_b = s.pin + L.b;
+            rgb::par_copy(s.pin + L.offsets, offsets + lp0, 8 * (size_t)(B + 1));
+            rgb::par_copy(s.pin + L.cx, cx + lp0, 4 * (size_t)B);
+            rgb::par_copy(s.pin + L.cy, cy + lp0, 4 * (size_t)B);
+            rgb::par_copy(s.pin + L.ax, ax + row0, 4 * (size_t)N);
+            rgb::par_copy(s.pin + L.ay, ay + row0, 4 * (size_t)N);
+            rgb::par_copy(s.pin + L.b, b + row0, 4 * (size_t)N);
+            src_off = s.pin_dev + L.offsets;
+            src_cx = s.pin_dev + L.cx;
+            src_cy = s.pin_dev + L.cy;
+            src_ax = s.pin_dev + L.ax;
+            src_ay = s.pin_dev + L.ay;
+            src_b = s.pin_dev + L.b;
         }
         bool ok = true;
         auto h2d = [&](size_t at, const char* src, size_t bytes) {
-            if (ok && bytes) ok = hipMemcpyAsync(s.dev + at, src, bytes, hipMemcpyHostToDevice, s.stream) == hipSuccess;
+            if (ok && bytes) ok = rgb::launch_copy(s.dev + at, src, bytes, s.stream);
         };
         h2d(L.offsets, src_off, 8 * (size_t)(B + 1));
         h2d(L.cx, src_cx, 4 * (size_t)B);
@@ -252,15 +324,11 @@ extern "C" rgb_err_t rgb_solve_batch_host(rgb_ctx_t* ctx, int64_t num_lps, int64
         }
         if (ok) {
             if (pin_out) {
-                ok = hipMemcpyAsync(x_out + lp0, s.dev + L.x, 4 * (size_t)B, hipMemcpyDeviceToHost, s.stream) ==
-                         hipSuccess &&
-                     hipMemcpyAsync(y_out + lp0, s.dev + L.y, 4 * (size_t)B, hipMemcpyDeviceToHost, s.stream) ==
-                         hipSuccess &&
-                     hipMemcpyAsync(status_out + lp0, s.dev + L.st, 4 * (size_t)B, hipMemcpyDeviceToHost,
-                                    s.stream) == hipSuccess;
+                ok = rgb::launch_copy(const_cast<char*>(d_x) + 4 * lp0, s.dev + L.x, 4 * (size_t)B, s.stream) &&
+                     rgb::launch_copy(const_cast<char*>(d_y) + 4 * lp0, s.dev + L.y, 4 * (size_t)B, s.stream) &&
+                     rgb::launch_copy(const_cast<char*>(d_st) + 4 * lp0, s.dev + L.st, 4 * (size_t)B, s.stream);
             } else {
-                ok = hipMemcpyAsync(s.pin + L.x, s.dev + L.x, L.total - L.x, hipMemcpyDeviceToHost, s.stream) ==
-                     hipSuccess;
+                ok = rgb::launch_copy(s.pin_dev + L.x, s.dev + L.x, L.total - L.x, s.stream);
             }
         }
         if (ok) ok = hipEventRecord(s.done, s.stream) == hipSuccess;

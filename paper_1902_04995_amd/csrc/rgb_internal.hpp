@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <string>
 #include <utility>
 
 #include "rgb_device.hpp"
@@ -46,8 +47,31 @@ struct PersistPlan {
     int chunk;
 };
 
+// One device's entry of a persisted tuning table (rgb_table.cpp): the
+// family and its scalar knobs, and lanes per LP for the size classes that
+// were tuned.
+struct TableEntry {
+    int variant = 3;
+    int log2_lanes[kClasses] = {};
+    bool tuned[kClasses] = {};
+    int batched_lanes = 16, queue_share = 128, chunk = 1, grid = 0;
+    int pool_lanes = 4, pool_wait = 2, pool_rows = 4;
+    double ms = 0.0;
+};
+// 1: entry found and applied to `out` (fields not in the file keep their
+// values), 0: no entry for the device (or no file), -1: unreadable table.
+int table_load(const char* path, const std::string& device_key, TableEntry& out);
+// Merge `e` into the table at `path` (created if missing); 0 or -1.
+int table_save(const char* path, const std::string& device_key, const TableEntry& e);
+
 // Device of a context (for the server, which only sees the opaque type).
 int ctx_device(const struct ::rgb_ctx* ctx);
+
+// Copy `bytes` bytes with a kernel on `stream` (not a DMA-engine copy), so
+// that the copy, the kernels around it and a completion event recorded after
+// it sit in one in-order queue.  Either side may be host memory given by its
+// device-visible address.  Returns false if the launch fails.
+bool launch_copy(void* dst, const void* src, size_t bytes, hipStream_t stream);
 
 // State of rgb_solve_batch_host (streams, device and pinned chunk buffers),
 // kept in the context and freed with it.
@@ -59,6 +83,8 @@ hipError_t launch_persistent(const Problem& P, const Workspace& W, const Persist
                              hipStream_t stream, hipEvent_t ev_begin, hipEvent_t ev_end);
 int persist_blocks_per_cu();
 hipError_t launch_plain(const Problem& P, hipStream_t stream);
+// The FP64 fix-up of LPs a fast kernel deferred; enqueued after every solve.
+hipError_t launch_fixup(const Problem& P, hipStream_t stream);
 hipError_t launch_group(const Problem& P, int lanes_per_lp, hipStream_t stream);
 bool group_supported(int lanes_per_lp);
 hipError_t launch_pool(const Problem& P, int lanes_per_lp, int rows_per_lane, int wait8, hipStream_t stream);

@@ -24,92 +24,6 @@
 namespace rgb {
 
 // ---------------------------------------------------------------------------
-// plain: one LP per lane
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ int serial_find(const float* rax, const float* ray, const float* rb, int v, const Line& L,
-                                           float target, bool up) {
-    for (int h = 0; h < v; ++h) {
-        float D;
-        float s = wu_sigma(rax[h], ray[h], rb[h], L, D);
-        if ((up ? D > 0.0f : D < 0.0f) && s == target) return h;
-    }
-    return kNoIdx;
-}
-
-__global__ __launch_bounds__(256) void k_plain(Problem P) {
-    int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= P.num_lps) return;
-    int64_t lp = P.order ? (int64_t)P.order[q] : q;
-    int64_t start;
-    int m;
-    LpState st;
-    float cx = P.cx[lp], cy = P.cy[lp];
-    init_state(st, cx, cy);
-    int n1d = 0;
-    if (!lp_range(P, lp, start, m) || !__builtin_isfinite(cx) || !__builtin_isfinite(cy)) {
-        set_dead(st, kInvalid);
-        finish_lp(P, lp, start, st, 0, 0);
-        return;
-    }
-    const float* rax = P.ax + start;
-    const float* ray = P.ay + start;
-    const float* rb = P.b + start;
-    bool bad = false;
-    int i = 0;
-    for (; i < m && st.kind != kDead; ++i) {
-        float ax = rax[i], ay = ray[i], b = rb[i];
-        if (!finite3(ax, ay, b)) {
-            bad = true;
-            break;
-        }
-        if (!row_violates(ax, ay, b, st)) continue;
-        ++n1d;
-        if (ax == 0.0f && ay == 0.0f) {  // 0 <= b with b < 0
-            set_dead(st, kInfeasible);
-            break;
-        }
-        Line L;
-        make_line(L, ax, ay, b);
-        float hi = __builtin_huge_valf(), lo = -__builtin_huge_valf();
-        for (int h = 0; h < i; ++h) work_unit(rax[h], ray[h], rb[h], L, hi, lo);
-        bool par = false;
-        if (hi == -__builtin_huge_valf()) {  // rare: a row parallel to line i, or an overflow
-            hi = __builtin_huge_valf();
-            lo = -__builtin_huge_valf();
-            for (int h = 0; h < i; ++h) work_unit_exact(rax[h], ray[h], rb[h], L, hi, lo, par);
-        }
-        if (par) {
-            set_dead(st, kInfeasible);
-            break;
-        }
-        if (!__builtin_isinf(hi) && !__builtin_isinf(lo)) {
-            bool inf = lo > hi;
-            if (near_tie(L, hi, lo)) {
-                int il = serial_find(rax, ray, rb, i, L, lo, false);
-                int ih = serial_find(rax, ray, rb, i, L, hi, true);
-                if (il != kNoIdx && ih != kNoIdx)
-                    inf = exact_lo_gt_hi(L, rax[il], ray[il], rb[il], rax[ih], ray[ih], rb[ih]);
-            }
-            if (inf) {
-                set_dead(st, kInfeasible);
-                break;
-            }
-        }
-        move_on_line(st, i, L, hi, lo, prefers_up(L, cx, cy));
-    }
-    for (++i; i < m && !bad; ++i) bad = !finite3(rax[i], ray[i], rb[i]);
-    if (bad) set_dead(st, kInvalid);
-    int h = -1;
-    if (st.kind == kPoint) {
-        Line L;
-        make_line(L, rax[st.l], ray[st.l], rb[st.l]);
-        h = serial_find(rax, ray, rb, st.l, L, st.sig, st.up);
-        if (h == kNoIdx) h = st.l;  // cannot happen (the bound came from these bits); x is NaN then
-    }
-    finish_lp(P, lp, start, st, h, n1d);
-}
-
-// ---------------------------------------------------------------------------
 // group: G lanes per LP
 // ---------------------------------------------------------------------------
 template <int CTRL>
@@ -210,9 +124,8 @@ struct RowRef {
 
 // Smallest row h < v of the LP whose bound on line L equals `target` on the
 // given side; all lanes of the group must be active.
-template <bool WIDE>
-__device__ __forceinline__ int group_find(const RowRef<WIDE>& R, int v, const Line& L, float target, bool up, int gl,
-                                          int lg) {
+template <class Rows>
+__device__ __forceinline__ int group_find(const Rows& R, int v, const Line& L, float target, bool up, int gl, int lg) {
     int best = kNoIdx;
     for (int h = gl; h < v; h += (1 << lg)) {
         float D;
@@ -223,24 +136,65 @@ __device__ __forceinline__ int group_find(const RowRef<WIDE>& R, int v, const Li
     return group_min_i(best, lg);
 }
 
-// After the bounds of a 1D LP are known on every lane of the group: the
-// rare exact rerun (hi = -inf flags a parallel row or an overflow), the
-// parallel-row and near-tie decisions, then the new state.
-template <bool WIDE>
-__device__ __forceinline__ void settle_1dlp(LpState& st, const RowRef<WIDE>& R, int v, const Line& L, float hi,
-                                            float lo, float cx, float cy, int gl, int lg, uint64_t gmask) {
-    bool par = false;
+// One side of the FP64 1D LP over rows 0 .. v-1 of line L, split over the
+// group's lanes and combined with a butterfly of shuffles; every lane gets
+// the group's bound.
+template <bool RIGHT, class Rows>
+__device__ __forceinline__ Bound64 group_exact(const Rows& R, int v, const Line& L, int gl, int lg) {
+    Bound64 e{0.0, RIGHT ? 1.0 : -1.0, -1};
+    for (int h = gl; h < v; h += (1 << lg)) exact_row<RIGHT>(e, L.lx, L.ly, L.lb, R.x(h), R.y(h), R.c(h), h);
+    for (int s = 1; s < (1 << lg); s <<= 1)
+        exact_merge<RIGHT>(e, __shfl_xor(e.N, s), __shfl_xor(e.D, s), __shfl_xor(e.I, s));
+    return e;
+}
+
+// After the fast pass of a 1D LP (bounds known on every lane of the group;
+// hi = -inf flags a parallel or overflowing row): the careful rerun when
+// flagged, the exact decision of a near tie from its two bounding rows, then
+// the new state.  A position that overflows FP32 needs the FP64 pass over the
+// whole 1D LP: with EXACT it runs here, otherwise the LP is deferred (it
+// stops with the internal status kDeferred and the fix-up kernel solves it
+// again with EXACT), which keeps that pass and its registers out of the fast
+// kernels.
+template <bool EXACT, class Rows>
+__device__ __forceinline__ void settle_1dlp(LpState& st, const Rows& R, int v, float hi, float lo, const Line& L,
+                                            float cx, float cy, int gl, int lg, uint64_t gmask) {
     if (hi == -__builtin_huge_valf()) {
+        bool par = false, ovf = false;
         hi = __builtin_huge_valf();
         lo = -__builtin_huge_valf();
-        for (int h = gl; h < v; h += (1 << lg)) work_unit_exact(R.x(h), R.y(h), R.c(h), L, hi, lo, par);
+        for (int h = gl; h < v; h += (1 << lg)) work_unit_exact(R.x(h), R.y(h), R.c(h), L, hi, lo, par, ovf);
         hi = group_min(hi, lg);
         lo = group_max(lo, lg);
-    }
-    par = (__ballot(par) & gmask) != 0;
-    if (par) {
-        set_dead(st, kInfeasible);
-        return;
+        if ((__ballot(par) & gmask) != 0) {
+            set_dead(st, kInfeasible);
+            return;
+        }
+        if ((__ballot(ovf) & gmask) != 0) {
+            if constexpr (!EXACT) {
+                set_dead(st, kDeferred);
+            } else {
+                const bool up = prefers_up(L, cx, cy);
+                const Bound64 eh = group_exact<true>(R, v, L, gl, lg);
+                const Bound64 el = group_exact<false>(R, v, L, gl, lg);
+                if (exact_empty(eh, el)) {
+                    set_dead(st, kInfeasible);
+                    return;
+                }
+                const int k = up ? eh.I : el.I;
+                float sig = up ? __builtin_huge_valf() : -__builtin_huge_valf();
+                if (k >= 0) {
+                    float D;
+                    sig = wu_sigma(R.x(k), R.y(k), R.c(k), L, D);
+                    if (!__builtin_isfinite(sig)) {  // the vertex lies beyond the FP32 range
+                        set_dead(st, kInvalid);
+                        return;
+                    }
+                }
+                move_to(st, v, L, sig, up);
+            }
+            return;
+        }
     }
     bool inf = false;
     if (!__builtin_isinf(hi) && !__builtin_isinf(lo)) {
@@ -278,12 +232,79 @@ __device__ __forceinline__ void finish_group(const Problem& P, int64_t lp, int64
     if (lp >= 0 && gl == 0) finish_lp(P, lp, start, st, h, n1d);
 }
 
+// ---------------------------------------------------------------------------
+// plain: one LP per lane
+// ---------------------------------------------------------------------------
+// Rows of one LP from its own pointers (one lane walks them serially).
+struct PtrRows {
+    const float* ax;
+    const float* ay;
+    const float* b;
+    __device__ __forceinline__ float x(int h) const { return ax[h]; }
+    __device__ __forceinline__ float y(int h) const { return ay[h]; }
+    __device__ __forceinline__ float c(int h) const { return b[h]; }
+};
+
+__global__ __launch_bounds__(256) void k_plain(Problem P) {
+    int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= P.num_lps) return;
+    int64_t lp = P.order ? (int64_t)P.order[q] : q;
+    int64_t start;
+    int m;
+    LpState st;
+    float cx = P.cx[lp], cy = P.cy[lp];
+    init_state(st, cx, cy);
+    int n1d = 0;
+    if (!lp_range(P, lp, start, m) || !__builtin_isfinite(cx) || !__builtin_isfinite(cy)) {
+        set_dead(st, kInvalid);
+        finish_lp(P, lp, start, st, 0, 0);
+        return;
+    }
+    const PtrRows R{P.ax + start, P.ay + start, P.b + start};
+    const uint64_t me = 1ull << __lane_id();
+    bool bad = false;
+    int i = 0;
+    for (; i < m && st.kind != kDead; ++i) {
+        float ax = R.x(i), ay = R.y(i), b = R.c(i);
+        if (!finite3(ax, ay, b)) {
+            bad = true;
+            break;
+        }
+        if (!row_violates(ax, ay, b, st)) continue;
+        if (ax == 0.0f && ay == 0.0f) {  // 0 <= b with b < 0
+            set_dead(st, kInfeasible);
+            break;
+        }
+        ++n1d;
+        Line L;
+        make_line(L, ax, ay, b);
+        float hi = __builtin_huge_valf(), lo = -__builtin_huge_valf(), chk = 0.0f;
+        for (int h = 0; h < i; ++h) work_unit(R.x(h), R.y(h), R.c(h), L, hi, lo, chk);
+        settle_1dlp<false>(st, R, i, flag_rerun(hi, chk), lo, L, cx, cy, 0, 0, me);
+    }
+    for (++i; i < m && !bad; ++i) bad = !finite3(R.x(i), R.y(i), R.c(i));
+    if (bad) set_dead(st, kInvalid);
+    int h = -1;
+    if (st.kind == kPoint) {
+        Line L;
+        make_line(L, R.x(st.l), R.y(st.l), R.c(st.l));
+        h = group_find(R, st.l, L, st.sig, st.up, 0, 0);
+        if (h == kNoIdx) h = st.l;  // cannot happen (the bound came from these bits); x is NaN then
+    }
+    finish_lp(P, lp, start, st, h, n1d);
+}
+
 // Solve the LP `lp` (-1: none) with a group of G = 2^lg lanes; every lane of
 // the wave calls this together, each group with its own LP.  LGC >= 0 fixes
 // lg at compile time; LGC = -1 takes it from lg_rt (one body for any width,
 // which keeps the persistent kernel's register count at one width's).
-template <int LGC, bool WIDE>
+// A scan step tests SR rows per lane (a window of SR G rows, loads issued
+// together); a 1D LP longer than two group widths folds U work units per
+// lane per step (U a multiple of 4, loads issued together).  More of either
+// means fewer dependent memory round trips per LP and more registers.
+template <int LGC, bool WIDE, bool EXACT = false, int SR = 1, int U = 4>
 __device__ __forceinline__ void solve_group(const Problem& P, int64_t lp, int lg_rt = 0) {
+    static_assert(SR >= 1 && U >= 4 && U % 4 == 0, "scan rows and work units per lane");
     const int lg = LGC >= 0 ? LGC : lg_rt;
     const int G = 1 << lg;
     const int lane = __lane_id();
@@ -311,58 +332,85 @@ __device__ __forceinline__ void solve_group(const Problem& P, int64_t lp, int lg
     int n1d = 0;
 
     while (__ballot(!done) != 0) {
-        // scan window: rows cur .. cur+G-1
-        int idx = cur + gl;
-        bool in = !done && idx < m;
-        float tx = 0.0f, ty = 0.0f, tb = 0.0f;
-        if (in) {
-            tx = R.x(idx);
-            ty = R.y(idx);
-            tb = R.c(idx);
+        // scan window: rows cur + gl + k G, k < SR
+        float tx[SR], ty[SR], tb[SR];
+        bool in[SR];
+#pragma unroll
+        for (int k = 0; k < SR; ++k) {
+            int idx = cur + gl + k * G;
+            in[k] = !done && idx < m;
+            tx[k] = ty[k] = tb[k] = 0.0f;
+            if (in[k]) {
+                tx[k] = R.x(idx);
+                ty[k] = R.y(idx);
+                tb[k] = R.c(idx);
+            }
         }
-        bool fin = finite3(tx, ty, tb);
-        bad |= in && !fin;
-        bool all_point = __ballot(in && st.kind != kPoint) == 0;
-        bool viol;
-        if (all_point) viol = in && point_violated(tx, ty, tb, st.px, st.py);
-        else viol = in && fin && row_violates(tx, ty, tb, st);
-        uint64_t bal = __ballot(viol) & gmask;
+        bool any_np = false;
+#pragma unroll
+        for (int k = 0; k < SR; ++k) any_np |= in[k];
+        const bool all_point = __ballot(any_np && st.kind != kPoint) == 0;
+        // the first violated row of the window: the smallest k with a hit, then
+        // the group's lowest lane
+        uint64_t bal = 0;
+        int ksel = 0;
+        float sx = 0.0f, sy = 0.0f, sb = 0.0f;
+#pragma unroll
+        for (int k = SR - 1; k >= 0; --k) {
+            bool fin = finite3(tx[k], ty[k], tb[k]);
+            bad |= in[k] && !fin;
+            bool viol;
+            if (all_point) viol = in[k] && point_violated(tx[k], ty[k], tb[k], st.px, st.py);
+            else viol = in[k] && fin && row_violates(tx[k], ty[k], tb[k], st);
+            uint64_t bk = __ballot(viol) & gmask;
+            if (bk != 0) {
+                bal = bk;
+                ksel = k;
+                sx = tx[k];
+                sy = ty[k];
+                sb = tb[k];
+            }
+        }
         if (bal == 0) {
             if (!done) {
-                cur += G;
+                cur += SR * G;
                 if (cur >= m) done = true;
             }
         } else {
             int src = __builtin_ctzll(bal);
-            int v = cur + (src - gbase);
-            float lx = __shfl(tx, src);
-            float ly = __shfl(ty, src);
-            float lb = __shfl(tb, src);
-            ++n1d;
+            int v = cur + ksel * G + (src - gbase);
+            float lx = __shfl(sx, src);
+            float ly = __shfl(sy, src);
+            float lb = __shfl(sb, src);
             if (lx == 0.0f && ly == 0.0f) {  // 0 <= b with b < 0
                 set_dead(st, kInfeasible);
             } else {
+                ++n1d;
                 Line L;
                 make_line(L, lx, ly, lb);
-                float hi = __builtin_huge_valf(), lo = -__builtin_huge_valf();
-                if (v > 2 * G) {  // long 1D LPs: four units per lane per step, loads issued together
-                    for (int h = gl; h < v; h += 4 * G) {
-                        float x[4], y[4], c[4];
+                float hi = __builtin_huge_valf(), lo = -__builtin_huge_valf(), chk = 0.0f;
+                if (v > 2 * G) {  // long 1D LPs: U units per lane per step, loads issued together
+                    for (int h = gl; h < v; h += U * G) {
+                        float x[U], y[U], c[U];
 #pragma unroll
-                        for (int k = 0; k < 4; ++k) {
+                        for (int k = 0; k < U; ++k) {
                             int hk = h + k * G < v ? h + k * G : v - 1;
                             x[k] = R.x(hk);
                             y[k] = R.y(hk);
                             c[k] = R.c(hk);
                         }
-                        work_units4(x, y, c, L, hi, lo);
+#pragma unroll
+                        for (int k = 0; k < U; k += 4)
+                            work_units4(*reinterpret_cast<const float(*)[4]>(x + k),
+                                        *reinterpret_cast<const float(*)[4]>(y + k),
+                                        *reinterpret_cast<const float(*)[4]>(c + k), L, hi, lo, chk);
                     }
                 } else {
-                    for (int h = gl; h < v; h += G) work_unit(R.x(h), R.y(h), R.c(h), L, hi, lo);
+                    for (int h = gl; h < v; h += G) work_unit(R.x(h), R.y(h), R.c(h), L, hi, lo, chk);
                 }
-                hi = group_min(hi, lg);
+                hi = group_min(flag_rerun(hi, chk), lg);
                 lo = group_max(lo, lg);
-                settle_1dlp(st, R, v, L, hi, lo, cx, cy, gl, lg, gmask);
+                settle_1dlp<EXACT>(st, R, v, hi, lo, L, cx, cy, gl, lg, gmask);
             }
             cur = v + 1;
             if (cur >= m || st.kind == kDead) done = true;
@@ -371,14 +419,32 @@ __device__ __forceinline__ void solve_group(const Problem& P, int64_t lp, int lg
     finish_group(P, lp, start, R, st, cur, m, bad, n1d, gl, lg, gmask);
 }
 
+// Eight waves per SIMD (at most 64 VGPRs): the scan and the work units wait
+// on memory, and more waves hide more of it.
 template <int G, bool WIDE>
-__global__ __launch_bounds__(256) void k_group(Problem P) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_group(Problem P) {
     constexpr int LPS_PER_BLOCK = 256 / G;
     int64_t q = (int64_t)blockIdx.x * LPS_PER_BLOCK + threadIdx.x / G;
     int64_t lp = -1;
     if (q < P.num_lps) lp = P.order ? (int64_t)P.order[q] : q;
     constexpr int LG = G == 4 ? 2 : G == 8 ? 3 : G == 16 ? 4 : G == 32 ? 5 : 6;
     solve_group<LG, WIDE>(P, lp);
+}
+
+// Fix-up pass after every solve: each wave looks at 64 statuses and solves
+// the deferred LPs among them again, one at a time with all 64 lanes and the
+// FP64 pass compiled in.  Deferred LPs are rare (near ties, overflow), so
+// this is mostly one coalesced read of the statuses.
+template <bool WIDE>
+__global__ __launch_bounds__(256) void k_fixup(Problem P) {
+    const int64_t base = (int64_t)blockIdx.x * 256 + (threadIdx.x & ~63);
+    const int64_t q = base + __lane_id();
+    uint64_t todo = __ballot(q < P.num_lps && P.status[q] == kDeferred);
+    while (todo != 0) {
+        const int k = __builtin_ctzll(todo);
+        todo &= todo - 1;
+        solve_group<6, WIDE, true>(P, base + k);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -481,7 +547,7 @@ __device__ __forceinline__ void pool_work_units(const Problem& P, PoolLds& S, in
         RowRef<WIDE> R{P.ax, P.ay, P.b, first};
         // four units per step with their loads issued together; indices past
         // the end repeat row v-1, which cannot change a min or a max
-        float hi = __builtin_huge_valf(), lo = -__builtin_huge_valf();
+        float hi = __builtin_huge_valf(), lo = -__builtin_huge_valf(), chk = 0.0f;
         for (int h = lane - L0; h < v; h += 4 * n) {
             float x[4], y[4], c[4];
 #pragma unroll
@@ -491,8 +557,9 @@ __device__ __forceinline__ void pool_work_units(const Problem& P, PoolLds& S, in
                 y[k] = R.y(hk);
                 c[k] = R.c(hk);
             }
-            work_units4(x, y, c, L, hi, lo);
+            work_units4(x, y, c, L, hi, lo, chk);
         }
+        hi = flag_rerun(hi, chk);
         if (hi != __builtin_huge_valf())
             __hip_atomic_fetch_min(&S.g[g].hi, fkey(hi), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
         if (lo != -__builtin_huge_valf())
@@ -590,7 +657,7 @@ __device__ __forceinline__ void solve_pool(const Problem& P, int64_t lp, int lg_
                     vy = __shfl(sy, src);
                     vb = __shfl(sb, src);
                     pend = true;
-                    ++n1d;
+                    n1d += (vx != 0.0f || vy != 0.0f) ? 1 : 0;  // a zero normal is no 1D LP
                 }
             }
         }
@@ -623,7 +690,7 @@ __device__ __forceinline__ void solve_pool(const Problem& P, int64_t lp, int lg_
                 set_dead(st, kInfeasible);
             } else {
                 float hi = funkey(S.g[grp].hi), lo = funkey(S.g[grp].lo);
-                settle_1dlp(st, R, v, L, hi, lo, cx, cy, gl, lg, gmask);
+                settle_1dlp<false>(st, R, v, hi, lo, L, cx, cy, gl, lg, gmask);
             }
             cur = v + 1;
             if (cur >= m || st.kind == kDead) done = true;
@@ -634,8 +701,9 @@ __device__ __forceinline__ void solve_pool(const Problem& P, int64_t lp, int lg_
     finish_group(P, lp, start, R, st, cur, m, bad, n1d, gl, lg, gmask);
 }
 
+// Six waves per SIMD (at most 80 VGPRs).
 template <int G, int RW, bool WIDE>
-__global__ __launch_bounds__(256) void k_pool(Problem P, int wait8) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_pool(Problem P, int wait8) {
     __shared__ PoolLds pool[4];
     constexpr int LPS_PER_BLOCK = 256 / G;
     int64_t q = (int64_t)blockIdx.x * LPS_PER_BLOCK + threadIdx.x / G;
@@ -834,6 +902,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
 // 32-bit byte offsets reach every row of the batch?
 static bool wide_rows(const Problem& P) { return P.num_constraints >= (int64_t(1) << 30); }
 
+hipError_t launch_fixup(const Problem& P, hipStream_t stream) {
+    if (P.num_lps == 0) return hipSuccess;
+    Problem F = P;
+    F.order = nullptr;
+    int64_t blocks = (P.num_lps + 255) / 256;
+    if (wide_rows(P)) hipLaunchKernelGGL(k_fixup<true>, dim3((unsigned)blocks), dim3(256), 0, stream, F);
+    else hipLaunchKernelGGL(k_fixup<false>, dim3((unsigned)blocks), dim3(256), 0, stream, F);
+    return hipGetLastError();
+}
+
 hipError_t launch_plain(const Problem& P, hipStream_t stream) {
     if (P.num_lps == 0) return hipSuccess;
     int64_t blocks = (P.num_lps + 255) / 256;
@@ -872,8 +950,10 @@ hipError_t launch_persistent(const Problem& P, const Workspace& W, const Persist
         if (wide) hipLaunchKernelGGL(k_persist<true>, dim3(grid), dim3(256), 0, stream, P, W, plan);
         else hipLaunchKernelGGL(k_persist<false>, dim3(grid), dim3(256), 0, stream, P, W, plan);
     }
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = launch_fixup(P, stream);
     if (ev_end) (void)hipEventRecord(ev_end, stream);
-    return hipGetLastError();
+    return e;
 }
 
 int persist_blocks_per_cu() {

@@ -43,20 +43,9 @@ using Clock = std::chrono::steady_clock;
 
 enum ReqState { kQueued = 0, kAdmitted = 1, kDone = 2, kFailed = 3 };
 
-// Copy n 32-bit words; either side may be host-mapped pinned memory.
-__global__ void k_copy_words(uint32_t* __restrict__ dst, const uint32_t* __restrict__ src, int64_t n) {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = src[i];
-}
-
 bool copy_words(void* dst, const void* src, size_t bytes, hipStream_t st) {
     if (bytes % 4 != 0) return false;  // every region of a Layout is a whole number of 16-byte lines
-    const int64_t n = (int64_t)(bytes / 4);
-    if (n == 0) return true;
-    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 2048);
-    hipLaunchKernelGGL(k_copy_words, dim3((unsigned)blocks), dim3(256), 0, st, static_cast<uint32_t*>(dst),
-                       static_cast<const uint32_t*>(src), n);
-    return hipGetLastError() == hipSuccess;
+    return rgb::launch_copy(dst, src, bytes, st);
 }
 
 struct Request {
@@ -332,7 +321,7 @@ rgb_err_t rgb_server_create(rgb_ctx_t* ctx, const rgb_server_opts_t* opts, rgb_s
     s->device = dev;
     // the server's own context on ctx's device, with ctx's tuning
     rgb_tuning_t t;
-    if (rgb_ctx_get_tuning(ctx, &t) != RGB_OK || rgb_ctx_create(dev, &s->ctx) != RGB_OK ||
+    if (rgb_ctx_get_tuning(ctx, &t) != RGB_OK || rgb_ctx_create(dev, nullptr, &s->ctx) != RGB_OK ||
         rgb_ctx_set_tuning(s->ctx, &t) != RGB_OK) {
         rgb_server_destroy(s);
         return RGB_ERR_DEVICE;

@@ -54,6 +54,34 @@ def golden_batch(path):
     return bt, [lp["expect"] for lp in lps], [lp["name"] for lp in lps]
 
 
+def rows_batch(lps, name="rows"):
+    """A gen.Batch from a list of (rows, (cx, cy)) with rows = [(ax, ay, b), ...]
+    given as Python or numpy floats (rounded to FP32)."""
+    from paper_1902_04995_amd import gen
+    sizes = [len(r) for r, _ in lps]
+    offs = np.zeros(len(lps) + 1, np.int64)
+    np.cumsum(sizes, out=offs[1:])
+    flat = np.array([x for r, _ in lps for x in r], np.float64).reshape(-1, 3)
+    return gen.Batch(offs, flat[:, 0].astype(np.float32), flat[:, 1].astype(np.float32),
+                     flat[:, 2].astype(np.float32), np.array([c[0] for _, c in lps], np.float32),
+                     np.array([c[1] for _, c in lps], np.float32), np.full(len(lps), gen.KIND_OTHER, np.int8), name)
+
+
+# LPs whose smallest decision gap in the oracle is below this may take another
+# path in FP32 (a different count of 1D LPs); their count is not compared.
+N1D_MARGIN = 1e-5
+
+
+def compare_n1d(n1d, ref, margin=N1D_MARGIN):
+    """(indices where the GPU's count of 1D LPs differs from the oracle's,
+    number of LPs left out) over LPs that are not INVALID and whose oracle
+    margin is at least `margin`."""
+    n1d = np.asarray(n1d)
+    keep = (np.asarray(ref["status"]) != INVALID) & (np.asarray(ref["margin"]) >= margin)
+    bad = np.flatnonzero(keep & (n1d != np.asarray(ref["n_1dlp"])))
+    return bad, int((~keep & (np.asarray(ref["status"]) != INVALID)).sum())
+
+
 def compare(status, x, y, ref_status, ref_x, ref_y, rtol=X_RTOL):
     """Indices where (status, x) disagrees with the reference under the parity bar."""
     status = np.asarray(status)

@@ -64,7 +64,7 @@ def test_null_context_errors_without_gpu():
     assert L.rgb_solve_batch(None, 0, 0, *([None] * 9), None, None) == -1
     assert L.rgb_ctx_last_error(None) == b"null context"
     assert L.rgb_ctx_destroy(None) == 0
-    assert L.rgb_ctx_create(0, None) == -1
+    assert L.rgb_ctx_create(0, None, None) == -1
 
 
 def test_null_handles_are_rejected_without_gpu():
@@ -72,7 +72,7 @@ def test_null_handles_are_rejected_without_gpu():
     import paper_1902_04995_amd as rgb
     L = rgb.lib()
     ERR, OK = -1, 0
-    assert L.rgb_autotune(None, 0, 0, *([None] * 9), 1, 1.0, None, None) == ERR
+    assert L.rgb_autotune(None, 0, 0, *([None] * 9), 1, 1.0, None, None, None) == ERR
     assert L.rgb_plan_create(None, 0, 0, *([None] * 9), None, None) == ERR
     assert L.rgb_plan_launch(None, None) == ERR
     assert L.rgb_plan_destroy(None) == OK
@@ -89,3 +89,21 @@ def test_null_handles_are_rejected_without_gpu():
     assert L.rgb_crowd_destroy(None) == OK
     # contention 3 is not a power of two: refused before anything is launched
     assert L.rgb_reduce_bench_run(2, 3, 0, None, None, None) == ERR
+
+
+def test_output_tensors_are_checked():
+    """Caller-supplied outputs must be float32/float32/int32, contiguous, on
+    the batch's device and hold one entry per LP (the kernels write that many)."""
+    import torch
+
+    import paper_1902_04995_amd as rgb
+    dev = torch.device("cpu")
+    ok = (torch.empty(5), torch.empty(5), torch.empty(5, dtype=torch.int32))
+    rgb._check_out(ok, 5, dev)
+    for bad in ((torch.empty(4), ok[1], ok[2]),                         # too short
+                (ok[0], torch.empty(5, dtype=torch.float64), ok[2]),    # wrong dtype
+                (ok[0], ok[1], torch.empty(5)),                         # status not int32
+                (torch.empty(10)[::2], ok[1], ok[2]),                   # not contiguous
+                (ok[0], ok[1])):                                        # missing one
+        with pytest.raises((TypeError, ValueError)):
+            rgb._check_out(bad, 5, dev)

@@ -49,14 +49,25 @@ def _run(rgb, bt, variant, g=0, s=0, n1d=False, rows=0):
 
 
 def _check(bt, ref, got, label, allow=0):
+    """Status bit-exact and x* within the bar against the oracle; when the
+    run returned the count of 1D LPs (got[3]), that count must equal the
+    oracle's on every LP the oracle decides with a margin of at least
+    lpcheck.N1D_MARGIN."""
     st, x, y = got[0], got[1].astype(np.float64), got[2].astype(np.float64)
     bs, bx = lpcheck.compare(st, x, y, ref["status"], ref["x"], ref["y"])
     msg = f"{label}: {len(bs)} status / {len(bx)} x mismatches of {bt.num_lps}"
-    if len(bs) or len(bx):
-        for k in list(bs[:5]) + list(bx[:5]):
+    bn, skipped = [], 0
+    if len(got) > 3:
+        bn, skipped = lpcheck.compare_n1d(got[3], ref)
+        msg += f"; {len(bn)} 1D-LP count mismatches ({skipped} LPs below the margin left out)"
+    if len(bs) or len(bx) or len(bn):
+        for k in list(bs[:5]) + list(bx[:5]) + list(bn[:5]):
             msg += (f"\n  lp {k} m={bt.sizes()[k]} got st={st[k]} x=({x[k]:.9g},{y[k]:.9g})"
                     f" ref st={ref['status'][k]} x=({ref['x'][k]:.9g},{ref['y'][k]:.9g}) margin={ref['margin'][k]:.3g}")
-    assert len(bs) + len(bx) <= allow, msg
+            if len(got) > 3:
+                msg += f" n1d={got[3][k]} ref n1d={ref['n_1dlp'][k]}"
+    _say(msg)
+    assert len(bs) + len(bx) + len(bn) <= allow, msg
     return msg
 
 
@@ -115,34 +126,120 @@ def test_parity_tiny_integer_degenerate(rgb, oracle_lib):
         _check(bt, ref, _run(rgb, bt, variant, g, s), f"tiny_int/{variant}")
 
 
-def test_edge_cases(rgb, oracle_lib):
+def _nonfinite_lps():
+    """Non-finite values in every field, before and after the row that
+    starts a 1D LP, in corner, ray and vertex states."""
+    lps = [([], (1.0, 0.0)),
+           ([(1, 0, 1), (0, 1, 1)], (np.inf, 1.0)),
+           ([(1, 0, 1), (0, 1, 1)], (1.0, -np.inf)),
+           ([(1, 0, 1), (0, 0, -1), (0, 1, 1)], (1.0, 1.0)),
+           ([(0, 0, 0), (1, 0, 1), (-1, 0, 1), (0, 1, 1), (0, -1, 1)], (1.0, 1.0))]
+    ring = [(np.cos(t), np.sin(t), 2.0) for t in np.linspace(0, 2 * np.pi, 90, endpoint=False)]
+    for bad in (np.inf, -np.inf, np.nan):
+        for field in range(3):
+            row = [0.5, 0.25, 1.0]
+            row[field] = bad
+            row = tuple(row)
+            base = [(1, 0, 1), (0, 1, 1), (1, 1, 1.5)]
+            for pos in range(4):  # first row (corner), after a ray, at the vertex, last
+                lps.append((base[:pos] + [row] + base[pos:], (1.0, 1.0)))
+            # in a long LP: windows with violations before and after it
+            lps.append((ring[:40] + [row] + ring[40:], (0.3, 0.7)))
+    return lps
+
+
+def _nextafter32(t, steps):
+    t = np.float32(t)
+    for _ in range(abs(steps)):
+        t = np.nextafter(t, np.float32(np.inf if steps > 0 else -np.inf))
+    return float(t)
+
+
+def _parallel_lps():
+    """A row parallel to the line of a later violated row, with offsets at the
+    FP32 neighbours of where the line's point lands (the parallel case of
+    Sec. 2.1 decided at the rounding of p0): x >= t and lx x <= 1 (empty iff
+    t > 1/lx), and a.x >= t with a.x <= 1 along other directions (empty iff
+    t > 1), in both orders, and after 100 far rows."""
+    lps = []
+    far = [(np.cos(t), np.sin(t), 50.0) for t in np.linspace(0, 2 * np.pi, 100, endpoint=False)]
+    for lx in range(1, 41):
+        for k in range(-2, 3):
+            t = _nextafter32(1.0 / lx, k)
+            h, l = (-1.0, 0.0, -t), (float(lx), 0.0, 1.0)
+            lps.append(([h, l], (1.0, 0.0)))
+            lps.append(([l, h], (1.0, 0.0)))
+            if lx % 4 == 1:
+                lps.append((far + [h, l], (1.0, 0.25)))
+    for ax, ay in [(1, 2), (3, -1), (-2, 5), (7, 3), (0, 3), (5, 0), (-4, -9)]:
+        for scale in (1.0, 2.0, 0.5, 3.0):
+            for k in range(-2, 3):
+                t = _nextafter32(1.0, k)
+                h = (-scale * ax, -scale * ay, -scale * t)
+                l = (float(ax), float(ay), 1.0)
+                lps.append(([h, l], (float(ax), float(ay))))
+                lps.append(([l, h], (float(ay), -float(ax))))
+    return lps
+
+
+def _range_lps():
+    """Positions beyond the FP32 range inside a 1D LP, and vertices beyond it."""
+    a, big = 1e-30, 1e10
+    lps = [
+        # y >= 1e-30 x + 1e10, x <= 5, x >= -5, then y <= 0: on y = 0 the first row
+        # bounds at x = -1e40 (an FP32 overflow) and the LP is infeasible
+        ([(a, -1, -big), (1, 0, 5), (-1, 0, 5), (0, 1, 0)], (0.0, -1.0)),
+        # a vertex at x = 1e40: INVALID; the same vertex on the way: INVALID
+        ([(1e-10, 0, 1e30), (0, 1, 1)], (1.0, 1.0)),
+        ([(1e-10, 0, 1e30), (0, 1, 1), (1, 0, 5)], (1.0, 1.0)),
+        # the far row only bounds a 1D LP from the side that is not chosen
+        ([(1, 0, 5), (1e-10, 0, 1e30), (0, 1, 1)], (1.0, 1.0)),
+        ([(1, 0, 3e38), (0, 1, 1)], (1.0, 1.0)),
+    ]
+    rng = np.random.default_rng(17)
+    for _ in range(300):  # small integer LPs with one or two rows of tiny slope and huge offset
+        m = int(rng.integers(3, 9))
+        rows = [tuple(float(v) for v in rng.integers(-4, 5, 3)) for _ in range(m)]
+        for _ in range(int(rng.integers(1, 3))):
+            s = float(rng.choice([-1, 1]))
+            rows.insert(int(rng.integers(0, len(rows) + 1)),
+                        (float(rng.integers(1, 5)) * a * s, float(rng.choice([-1, 1])),
+                         float(rng.integers(-3, 4)) * big))
+        lps.append((rows, tuple(float(v) for v in rng.integers(-3, 4, 2))))
+    return lps
+
+
+EDGE_SETS = {"nonfinite": _nonfinite_lps, "parallel": _parallel_lps, "range": _range_lps}
+
+
+def test_empty_batch(rgb):
     import torch
-    # empty batch
     dev = torch.device("cuda:0")
     z64 = torch.zeros(1, dtype=torch.int64, device=dev)
     e32 = torch.empty(0, dtype=torch.float32, device=dev)
     for variant in ("plain", "batched", "persistent", "binned", "pooled"):
         x, y, st = rgb.solve_batch(z64, e32, e32, e32, e32, e32, variant=variant)
         assert x.numel() == 0
-    # LPs with no rows, NaN / inf rows and objectives, zero normals
-    rows = [
-        ([], (1.0, 0.0)),
-        ([(1, 0, 1), (np.nan, 0, 1)], (1.0, 1.0)),
-        ([(1, 0, 1), (0, 1, 1)], (np.inf, 1.0)),
-        ([(1, 0, 1), (0, 0, -1), (0, 1, 1)], (1.0, 1.0)),
-        ([(0, 0, 0), (1, 0, 1), (-1, 0, 1), (0, 1, 1), (0, -1, 1)], (1.0, 1.0)),
-    ]
-    sizes = [len(r) for r, _ in rows]
-    offs = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
-    flat = np.array([x for r, _ in rows for x in r], np.float64).reshape(-1, 3)
-    bt = gen.Batch(offs, flat[:, 0].astype(np.float32), flat[:, 1].astype(np.float32), flat[:, 2].astype(np.float32),
-                   np.array([c[0] for _, c in rows], np.float32), np.array([c[1] for _, c in rows], np.float32),
-                   np.zeros(len(rows), np.int8))
+
+
+@pytest.mark.parametrize("edge", list(EDGE_SETS))
+def test_edge_cases(rgb, oracle_lib, edge):
+    bt = lpcheck.rows_batch(EDGE_SETS[edge](), edge)
     ref = oracle_lib.solve(bt)
-    assert ref["status"].tolist() == [2, 3, 3, 1, 0]
+    if edge == "nonfinite":
+        assert ref["status"][:5].tolist() == [2, 3, 3, 1, 0]
+        assert np.all(ref["status"][5:] == 3)
+    if edge == "range":
+        assert ref["status"][:5].tolist() == [1, 3, 3, 0, 0]
+    base = None
     for variant, g, s in SHAPES:
-        _say(f"[gpu] case=edge variant={variant} G={g} S={s}")
-        _check(bt, ref, _run(rgb, bt, variant, g, s), f"edge/{variant}")
+        _say(f"[gpu] case=edge/{edge} variant={variant} G={g} S={s} lps={bt.num_lps}")
+        got = _run(rgb, bt, variant, g, s, n1d=True)
+        _check(bt, ref, got, f"edge/{edge}/{variant}/{g}x{s}")
+        if base is None:
+            base = got
+        for a, b_ in zip(got[:3], base[:3]):
+            assert np.array_equal(a, b_, equal_nan=True), f"edge/{edge}: {variant}/{g} differs from plain"
 
 
 def test_malformed_offsets_are_invalid_not_read(rgb):
@@ -189,28 +286,32 @@ def test_one_huge_lp(rgb, oracle_lib):
             assert np.array_equal(a, b_, equal_nan=True)
 
 
-# the launches the benchmark's autotuner picks for each workload (batched at
-# 16 lanes on uniform, 8 on crowd, binned on uneven), and the other families
+# the launches the benchmark's autotuner has picked for each workload
+# (batched at 16 lanes on uniform, 8 on crowd, binned on uneven), and the
+# other families
 FULL = [("uniform", "batched", 16), ("crowd", "batched", 8), ("uneven", "binned", 0)] + \
     [(n, v, 0) for n in ("uniform", "uneven", "crowd") for v in ("persistent", "pooled")]
+_FULL_CACHE = {}
 
 
-@pytest.mark.parametrize("name,variant,g", FULL)
-def test_full_size_sampled(rgb, oracle_lib, name, variant, g):
-    """Full-size workloads in the benchmark's launch configurations, checked
-    on a sample of LPs the oracle solves one by one."""
-    bt = gen.make_config(name, seed=0)
+def _full(name, oracle_lib):
+    if name not in _FULL_CACHE:
+        _FULL_CACHE.clear()
+        bt = gen.make_config(name, seed=0)
+        _FULL_CACHE[name] = (bt, oracle_lib.solve(bt))
+    return _FULL_CACHE[name]
+
+
+@pytest.mark.parametrize("name,variant,g", sorted(FULL))
+def test_full_size_every_lp(rgb, oracle_lib, name, variant, g):
+    """Full-size workloads in the benchmark's launch configurations: status,
+    x* and the count of 1D LPs of every LP against the oracle's solve of the
+    whole batch."""
+    bt, ref = _full(name, oracle_lib)
     _say(f"[gpu] case=full {name} variant={variant} lanes={g} lps={bt.num_lps} rows={bt.num_constraints}")
-    got = _run(rgb, bt, variant, g)
-    rng = np.random.default_rng(1)
-    idx = np.sort(rng.choice(bt.num_lps, size=min(4000, bt.num_lps), replace=False))
-    sub = bt.subset(idx)
-    ref = oracle_lib.solve(sub)
-    _check(sub, ref, [got[0][idx], got[1][idx], got[2][idx]], f"full/{name}")
-    # whole-batch properties: every LP got a definite status; the construction
-    # tags hold (boxed -> optimal, injected pair -> infeasible, half circle -> unbounded)
+    got = _run(rgb, bt, variant, g, n1d=True)
+    _check(bt, ref, got, f"full/{name}/{variant}/{g}")
     st = got[0]
-    assert np.all((st >= 0) & (st <= 2))
     if name != "crowd":
         assert np.all(st[bt.kind == gen.KIND_BOXED] == OPTIMAL)
         assert np.all(st[bt.kind == gen.KIND_INFEASIBLE] == 1)

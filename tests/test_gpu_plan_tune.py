@@ -125,3 +125,76 @@ def test_two_plans_overlap_on_two_streams(rgb):
             assert np.array_equal(a, b, equal_nan=True)
     p1.close()
     p2.close()
+
+
+_CHILD = r"""
+import json, sys
+import numpy as np
+sys.path.insert(0, sys.argv[1])
+import torch
+import paper_1902_04995_amd as rgb
+from paper_1902_04995_amd import gen
+z = np.load(sys.argv[3])
+bt = gen.Batch(z["offsets"], z["ax"], z["ay"], z["b"], z["cx"], z["cy"], z["kind"], "t")
+ctx = rgb.Context(0, tuning_table=sys.argv[2])
+x, y, st = rgb.DeviceBatch(bt, "cuda:0").solve(variant="auto", ctx=ctx)
+torch.cuda.synchronize()
+np.savez(sys.argv[4], x=x.cpu().numpy(), y=y.cpu().numpy(), st=st.cpu().numpy())
+print(json.dumps(ctx.tuning.to_dict()))
+"""
+
+
+def test_tuning_table_persists_across_processes(rgb, tmp_path):
+    """rgb_autotune merges its result into a JSON table keyed by device and
+    size class; a fresh process that creates its context from the table
+    solves with that configuration (no search) and gets the same bits."""
+    import json
+    import os
+    import subprocess
+
+    import torch
+    bt = gen.uneven_batch(4000, 8, 3000, seed=9)
+    dev = rgb.DeviceBatch(bt, "cuda:0")
+    table = str(tmp_path / "tuning.json")
+    ctx = rgb.Context(0)
+    _say("[gpu] autotune with a table")
+    best = dev.autotune(reps=2, budget_ms=1500.0, ctx=ctx, table_path=table)
+    got = _host(dev.solve(variant="auto", ctx=ctx))
+    torch.cuda.synchronize()
+    doc = json.load(open(table))
+    assert doc["format"] == "rgb-tuning-1" and len(doc["devices"]) == 1
+    (key, entry), = doc["devices"].items()
+    assert "gfx950" in key and entry["variant"] == best.to_dict()["variant"]
+    assert entry["classes"], "no size class was tuned"
+    np.savez(tmp_path / "batch.npz", offsets=bt.offsets, ax=bt.ax, ay=bt.ay, b=bt.b, cx=bt.cx, cy=bt.cy,
+             kind=bt.kind)
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    _say("[gpu] fresh process from the table")
+    r = subprocess.run([sys.executable, "-c", _CHILD, root, table, str(tmp_path / "batch.npz"),
+                        str(tmp_path / "out.npz")], capture_output=True, text=True, timeout=240)
+    assert r.returncode == 0, r.stderr[-2000:]
+    child = json.loads(r.stdout.strip().splitlines()[-1])
+    want = best.to_dict()
+    assert child["variant"] == want["variant"]
+    for c, v in entry["classes"].items():
+        assert child["log2_lanes"][int(c)] == v["log2_lanes"]
+    for k in ("batched_lanes", "queue_share", "chunk", "pool_lanes", "pool_wait", "pool_rows"):
+        assert child[k] == want[k], k
+    out = np.load(tmp_path / "out.npz")
+    for a, b_ in zip((out["x"], out["y"], out["st"]), got):
+        assert np.array_equal(a, b_, equal_nan=True)
+    # a second tuning run on another batch keeps the classes it did not measure
+    small = rgb.DeviceBatch(gen.uniform_batch(3000, 60, seed=2), "cuda:0")
+    small.autotune(reps=2, budget_ms=800.0, ctx=rgb.Context(0), table_path=table)
+    doc2 = json.load(open(table))
+    (entry2,) = doc2["devices"].values()
+    for c in entry["classes"]:
+        assert c in entry2["classes"]
+    # a missing table leaves the defaults; an unreadable one is refused
+    assert rgb.Context(0, tuning_table=str(tmp_path / "missing.json")).tuning.to_dict() == \
+        rgb.Context(0).tuning.to_dict()
+    bad = tmp_path / "bad.json"
+    bad.write_text("{not json")
+    with pytest.raises(rgb.RgbError):
+        rgb.Context(0, tuning_table=str(bad))
+    ctx.close()

@@ -69,6 +69,40 @@ def test_alone_vs_mix(rgb, oracle_lib):
     srv.close()
 
 
+def test_alone_vs_mix_full_request_shapes(rgb, oracle_lib):
+    """The served request mix at its full shapes (floor(logU[1, 4096]) LPs per
+    request, random rows log-uniform in [16, 2048] plus the box, 5% infeasible,
+    2% unbounded) under the default server options: every request's result
+    equals its solve alone bit for bit and meets the bar against the oracle."""
+    import torch
+    rng = gen.rng_for(5, 7)
+    reqs = [gen.served_request(rng) for _ in range(48)]
+    _say(f"[gpu] served full shapes: {sum(r.num_lps for r in reqs)} LPs, "
+         f"{sum(r.num_constraints for r in reqs)} rows, largest request {max(r.num_lps for r in reqs)} LPs")
+    alone = []
+    for r in reqs:
+        x, y, st = rgb.DeviceBatch(r, "cuda:0").solve()
+        torch.cuda.synchronize()
+        alone.append((x.cpu().numpy(), y.cpu().numpy(), st.cpu().numpy()))
+    srv = rgb.Server()
+    tickets = []
+    for i, r in enumerate(reqs):
+        tickets.append(srv.submit(r, wait=True))
+        if i % 5 == 2:
+            time.sleep(0.001)  # some arrive while others run
+    res = [srv.wait(t) for t in tickets]
+    stats = srv.stats()
+    _say(f"[gpu] server stats {stats}")
+    assert stats["completed"] == len(reqs) and stats["micro_batches"] < len(reqs)
+    for k, (r, (x, y, st, lat), (ax_, ay_, as_)) in enumerate(zip(reqs, res, alone)):
+        assert np.array_equal(st, as_), k
+        assert np.array_equal(x, ax_, equal_nan=True) and np.array_equal(y, ay_, equal_nan=True), k
+        ref = oracle_lib.solve(r)
+        bs, bx = lpcheck.compare(st, x, y, ref["status"], ref["x"], ref["y"])
+        assert len(bs) == 0 and len(bx) == 0, (k, bs[:5], bx[:5])
+    srv.close()
+
+
 def test_budget_and_backpressure(rgb):
     # one stream, the plain kernel: a request of four 16,384-row LPs keeps the
     # stream busy for milliseconds (each LP is one lane's serial work), so the

@@ -110,7 +110,7 @@ typedef struct {
     int32_t grid;           /* PERSISTENT: workgroups launched */
     int32_t queue_share;    /* PERSISTENT: share of the sub-batches handed out by the device queue,
                                in 1/1024 (the rest are dealt round-robin); -1 = none */
-    int32_t* n_1dlp_out;    /* optional device int32[num_lps]: 1D LPs solved per LP */
+    int32_t* n_1dlp_out;    /* optional device int32[num_lps]: 1D LPs solved per LP (0 for INVALID LPs) */
     void* ev_begin;         /* optional hipEvent_t recorded on the stream right before the solve kernel */
     void* ev_end;           /* optional hipEvent_t recorded right after it and the FP64 fix-up kernel
                                that follows every solve (binning kernels excluded) */
@@ -122,7 +122,10 @@ typedef struct {
     int32_t variant;        /* RGB_VARIANT_PERSISTENT, _BINNED, _BATCHED or _POOLED */
     int32_t log2_lanes[16]; /* PERSISTENT/BINNED: lanes per LP = 2^v (v in 2..6) for size class c,
                                which holds LPs with 2^(c-1) < m <= 2^c rows (class 0: m <= 1,
-                               class 15: m > 2^14) */
+                               class 15: m > 2^14); v = 8: each LP of the class is solved by a
+                               workgroup of 128 lanes (two waves) that keeps the LP's first
+                               1,650 rows in LDS (Sec. 3's block-wide work units), before the
+                               other classes */
     int32_t batched_lanes;  /* BATCHED: lanes per LP (4, 8, 16, 32 or 64) */
     int32_t queue_share;    /* PERSISTENT: sub-batches handed out by the device queue, in 1/1024 */
     int32_t chunk;          /* PERSISTENT: sub-batches per queue pop (>= 1) */

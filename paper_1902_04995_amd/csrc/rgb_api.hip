@@ -29,11 +29,13 @@ constexpr int kMaxStreams = 32;
 
 }  // namespace
 
+
 struct rgb_ctx {
     int device = 0;
     std::string device_key;  // "<name> <arch> <CUs>cu": the tuning table's key
     int num_cus = 0;
     int persist_blocks_per_cu = 1;
+    int wide_blocks_per_cu = 1;
     rgb_tuning_t tuning{};
     std::vector<WsSlot> slots;
     rgb::HostPath* host = nullptr;  // rgb_solve_batch_host state, made on first use
@@ -102,7 +104,7 @@ bool tuning_valid(const rgb_tuning_t& t) {
         t.variant != RGB_VARIANT_POOLED)
         return false;
     for (int c = 0; c < rgb::kClasses; ++c)
-        if (t.log2_lanes[c] < 2 || t.log2_lanes[c] > 6) return false;
+        if ((t.log2_lanes[c] < 2 || t.log2_lanes[c] > 6) && t.log2_lanes[c] != rgb::kWideLg) return false;
     return lanes_ok(t.batched_lanes) && t.queue_share >= 0 && t.queue_share <= 1024 && t.chunk >= 1 &&
            t.grid >= 0 && rgb::pool_supported(t.pool_lanes, t.pool_rows) && t.pool_wait >= 0 && t.pool_wait <= 8;
 }
@@ -162,12 +164,13 @@ rgb_err_t grow_workspace(rgb_ctx_t* ctx, WsSlot& slot, int64_t num_lps) {
         slot.mem = nullptr;
         slot.cap = 0;
     }
+    // No clearing: the binning kernels of every solve write each field before
+    // any kernel reads it.  A host-side clear would also be unordered with
+    // the caller's stream: a hipMemset goes to the null stream, which a
+    // non-blocking stream does not wait for, so it could land after this
+    // solve's queue set-up and empty the queue.
     void* mem = nullptr;
     if (hipMalloc(&mem, total) != hipSuccess) return fail(ctx, RGB_ERR_OOM, "workspace of %zu bytes", total);
-    if (hipMemset(mem, 0, head_bytes) != hipSuccess) {
-        (void)hipFree(mem);
-        return fail(ctx, RGB_ERR_DEVICE, "workspace init failed");
-    }
     char* base = static_cast<char*>(mem);
     slot.mem = mem;
     slot.cap = cap;
@@ -294,7 +297,8 @@ rgb_err_t enqueue(rgb_ctx_t* ctx, const rgb::Problem& P, int variant, const rgb_
         plan.dyn_frac_1024 = cfg.queue_share;
         plan.chunk = cfg.chunk;
         int grid = cfg.grid ? cfg.grid : ctx->num_cus * ctx->persist_blocks_per_cu;
-        e = rgb::launch_persistent(P, *W, plan, grid, variant == RGB_VARIANT_BINNED, st, ev0, ev1);
+        e = rgb::launch_persistent(P, *W, plan, grid, ctx->num_cus * ctx->wide_blocks_per_cu,
+                                   variant == RGB_VARIANT_BINNED, st, ev0, ev1);
     }
     if (e != hipSuccess) return fail(ctx, RGB_ERR_DEVICE, "launch failed: %s", hipGetErrorString(e));
     return RGB_OK;
@@ -329,6 +333,7 @@ rgb_err_t rgb_ctx_create(int device, const rgb_ctx_opts_t* opts, rgb_ctx_t** out
     arch = arch.substr(0, arch.find(':'));
     ctx->device_key = std::string(prop.name) + " " + arch + " " + std::to_string(prop.multiProcessorCount) + "cu";
     ctx->persist_blocks_per_cu = rgb::persist_blocks_per_cu();
+    ctx->wide_blocks_per_cu = rgb::wide_blocks_per_cu();
     default_tuning(ctx->tuning);
     if (opts && opts->tuning_table) {
         rgb::TableEntry e = table_entry_of(ctx->tuning);
@@ -515,7 +520,7 @@ rgb_err_t rgb_autotune(rgb_ctx_t* ctx, int64_t num_lps, int64_t num_constraints,
             if (elapsed_ms() > budget_ms) break;
             float best_ms = 1e30f;
             for (int v : {RGB_VARIANT_PERSISTENT, RGB_VARIANT_BINNED})
-                for (int lg = 2; lg <= 6; ++lg) {
+                for (int lg : {2, 3, 4, 5, 6, rgb::kWideLg}) {
                     rgb_tuning_t cand = base;
                     cand.variant = v;
                     cand.log2_lanes[c] = lg;

@@ -446,7 +446,10 @@ rgb_err_t rgb_crowd_create(rgb_ctx_t* ctx, int64_t n_agents, const int32_t* k, c
         if (hipMemcpy(c->k, k, 4 * n_, hipMemcpyHostToDevice) != hipSuccess ||
             hipMemcpy(c->offsets, offs.data(), 8 * (n_ + 1), hipMemcpyHostToDevice) != hipSuccess ||
             hipMemcpy(c->disc, disc.data(), 4 * disc.size(), hipMemcpyHostToDevice) != hipSuccess ||
-            hipMemset(c->counter, 0, 8) != hipSuccess)
+            hipMemset(c->counter, 0, 8) != hipSuccess ||
+            // these run on the null stream, which a non-blocking stream does not
+            // wait for: finish them before any step can be enqueued
+            hipDeviceSynchronize() != hipSuccess)
             rc = RGB_ERR_DEVICE;
     }
     if (c->device != prev) (void)hipSetDevice(prev);

@@ -407,7 +407,9 @@ __device__ __forceinline__ void finish_lp(const Problem& P, int64_t lp, int64_t 
     P.x_out[lp] = x;
     P.y_out[lp] = y;
     P.status[lp] = status;
-    if (P.n1d) P.n1d[lp] = n1d;
+    // the count is that of the method's path; an INVALID LP has none (kernels
+    // stop at different rows once they see a non-finite value)
+    if (P.n1d) P.n1d[lp] = status == kInvalid ? 0 : n1d;
 }
 
 // Row range of LP lp, checked against the row arrays.  Returns false (and

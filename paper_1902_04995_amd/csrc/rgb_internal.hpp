@@ -16,14 +16,21 @@ constexpr int kClasses = 16;     // LP size classes: ceil(log2 m), capped
 constexpr int kBinBlocks = 256;  // blocks of the binning passes
 constexpr int kQueues = 8;       // device queue parts (one per XCD of an MI355X)
 constexpr int kHeadStride = 32;  // ints between queue heads (one 128-byte line each)
+// log2_lanes value of a size class whose LPs are each solved by one whole
+// workgroup with its rows staged in LDS (the wide kernel), not by a group of
+// 4..64 lanes.
+constexpr int kWideLg = 8;
 
-// Queue description written by the scan pass: classes in queue order
-// (largest first), their entry ranges in `order`, and the cumulative count
-// of sub-batches (64/G LPs each).
+// Queue description written by the scan pass: classes in queue order (the
+// wide classes first, then the others, each part largest first), their entry
+// ranges in `order`, and the cumulative count of sub-batches (64/G LPs each;
+// a wide class has none: its LPs are entries [0, n_wide) of the queue, taken
+// by the wide kernel through wide_head).
 struct QueueHeader {
     int num_sb;     // sub-batches in total
     int dyn_begin;  // first sub-batch handed out by the queue
-    int pad[2];
+    int n_wide;     // LPs of the wide classes
+    int wide_head;  // next of them to take (reset by the scan pass)
     int e_start[kClasses];
     int e_end[kClasses];
     int sb_end[kClasses];
@@ -79,9 +86,12 @@ struct HostPath;
 HostPath*& ctx_host_path(struct ::rgb_ctx* ctx);
 void destroy_host_path(HostPath* h);
 
-hipError_t launch_persistent(const Problem& P, const Workspace& W, const PersistPlan& plan, int grid, bool binned,
-                             hipStream_t stream, hipEvent_t ev_begin, hipEvent_t ev_end);
+// The binned or persistent solve: binning, queue set-up, the wide kernel
+// (wide_grid workgroups) when a class is wide, then the group kernel.
+hipError_t launch_persistent(const Problem& P, const Workspace& W, const PersistPlan& plan, int grid, int wide_grid,
+                             bool binned, hipStream_t stream, hipEvent_t ev_begin, hipEvent_t ev_end);
 int persist_blocks_per_cu();
+int wide_blocks_per_cu();
 hipError_t launch_plain(const Problem& P, hipStream_t stream);
 // The FP64 fix-up of LPs a fast kernel deferred; enqueued after every solve.
 hipError_t launch_fixup(const Problem& P, hipStream_t stream);

@@ -94,6 +94,10 @@ __device__ __forceinline__ int group_min_i(int v, int lg) {
     return v;
 }
 
+// Compiler-level ordering of LDS accesses between lanes of one wave (the LDS
+// executes one wave's instructions in order).
+__device__ __forceinline__ void wave_lds_order() { __atomic_signal_fence(__ATOMIC_SEQ_CST); }
+
 __device__ __forceinline__ uint64_t group_mask(int lg, int gbase) {
     return lg >= 6 ? ~0ull : (((1ull << (1 << lg)) - 1ull) << gbase);
 }
@@ -122,18 +126,35 @@ struct RowRef {
     __device__ __forceinline__ float c(int h) const { return ld(b, h); }
 };
 
+// The lanes that work on one LP together, as the 1D-LP helpers below see
+// them: lane `first()` of `step()` lanes takes rows first(), first() + step(),
+// ...; min/max/imin/any combine a value over those lanes and give every one
+// of them the result.  GroupLanes is an aligned group of G = 2^lg lanes of a
+// wave (DPP butterflies and ballots); the wide kernel's workgroup has its own.
+struct GroupLanes {
+    int gl, lg;
+    uint64_t gmask;
+    __device__ __forceinline__ int first() const { return gl; }
+    __device__ __forceinline__ int step() const { return 1 << lg; }
+    __device__ __forceinline__ float min(float v) const { return group_min(v, lg); }
+    __device__ __forceinline__ float max(float v) const { return group_max(v, lg); }
+    __device__ __forceinline__ int imin(int v) const { return group_min_i(v, lg); }
+    __device__ __forceinline__ bool any(bool b) const { return (__ballot(b) & gmask) != 0; }
+};
+
 // Smallest row h < v of the LP whose bound on line L equals `target` on the
-// given side; all lanes of the group must be active.
-template <class Rows>
-__device__ __forceinline__ int group_find(const Rows& R, int v, const Line& L, float target, bool up, int gl, int lg) {
+// given side; all cooperating lanes must be active.
+template <class Rows, class Lanes>
+__device__ __forceinline__ int group_find(const Rows& R, int v, const Line& L, float target, bool up,
+                                          const Lanes& ln) {
     int best = kNoIdx;
-    for (int h = gl; h < v; h += (1 << lg)) {
+    for (int h = ln.first(); h < v; h += ln.step()) {
         float D;
         float s = wu_sigma(R.x(h), R.y(h), R.c(h), L, D);
         bool hit = (up ? D > 0.0f : D < 0.0f) && s == target;
         best = (hit && h < best) ? h : best;
     }
-    return group_min_i(best, lg);
+    return ln.imin(best);
 }
 
 // One side of the FP64 1D LP over rows 0 .. v-1 of line L, split over the
@@ -148,35 +169,35 @@ __device__ __forceinline__ Bound64 group_exact(const Rows& R, int v, const Line&
     return e;
 }
 
-// After the fast pass of a 1D LP (bounds known on every lane of the group;
+// After the fast pass of a 1D LP (bounds known on every cooperating lane;
 // hi = -inf flags a parallel or overflowing row): the careful rerun when
 // flagged, the exact decision of a near tie from its two bounding rows, then
 // the new state.  A position that overflows FP32 needs the FP64 pass over the
-// whole 1D LP: with EXACT it runs here, otherwise the LP is deferred (it
-// stops with the internal status kDeferred and the fix-up kernel solves it
-// again with EXACT), which keeps that pass and its registers out of the fast
-// kernels.
-template <bool EXACT, class Rows>
+// whole 1D LP: with EXACT it runs here (a group of one wave only), otherwise
+// the LP is deferred (it stops with the internal status kDeferred and the
+// fix-up kernel solves it again with EXACT), which keeps that pass and its
+// registers out of the fast kernels.
+template <bool EXACT, class Rows, class Lanes>
 __device__ __forceinline__ void settle_1dlp(LpState& st, const Rows& R, int v, float hi, float lo, const Line& L,
-                                            float cx, float cy, int gl, int lg, uint64_t gmask) {
+                                            float cx, float cy, const Lanes& ln) {
     if (hi == -__builtin_huge_valf()) {
         bool par = false, ovf = false;
         hi = __builtin_huge_valf();
         lo = -__builtin_huge_valf();
-        for (int h = gl; h < v; h += (1 << lg)) work_unit_exact(R.x(h), R.y(h), R.c(h), L, hi, lo, par, ovf);
-        hi = group_min(hi, lg);
-        lo = group_max(lo, lg);
-        if ((__ballot(par) & gmask) != 0) {
+        for (int h = ln.first(); h < v; h += ln.step()) work_unit_exact(R.x(h), R.y(h), R.c(h), L, hi, lo, par, ovf);
+        hi = ln.min(hi);
+        lo = ln.max(lo);
+        if (ln.any(par)) {
             set_dead(st, kInfeasible);
             return;
         }
-        if ((__ballot(ovf) & gmask) != 0) {
+        if (ln.any(ovf)) {
             if constexpr (!EXACT) {
                 set_dead(st, kDeferred);
             } else {
                 const bool up = prefers_up(L, cx, cy);
-                const Bound64 eh = group_exact<true>(R, v, L, gl, lg);
-                const Bound64 el = group_exact<false>(R, v, L, gl, lg);
+                const Bound64 eh = group_exact<true>(R, v, L, ln.gl, ln.lg);
+                const Bound64 el = group_exact<false>(R, v, L, ln.gl, ln.lg);
                 if (exact_empty(eh, el)) {
                     set_dead(st, kInfeasible);
                     return;
@@ -200,8 +221,8 @@ __device__ __forceinline__ void settle_1dlp(LpState& st, const Rows& R, int v, f
     if (!__builtin_isinf(hi) && !__builtin_isinf(lo)) {
         inf = lo > hi;
         if (near_tie(L, hi, lo)) {
-            int il = group_find(R, v, L, lo, false, gl, lg);
-            int ih = group_find(R, v, L, hi, true, gl, lg);
+            int il = group_find(R, v, L, lo, false, ln);
+            int ih = group_find(R, v, L, hi, true, ln);
             if (il != kNoIdx && ih != kNoIdx)
                 inf = exact_lo_gt_hi(L, R.x(il), R.y(il), R.c(il), R.x(ih), R.y(ih), R.c(ih));
         }
@@ -225,7 +246,7 @@ __device__ __forceinline__ void finish_group(const Problem& P, int64_t lp, int64
         if (st.kind == kPoint) {
             Line L;
             make_line(L, R.x(st.l), R.y(st.l), R.c(st.l));
-            h = group_find(R, st.l, L, st.sig, st.up, gl, lg);
+            h = group_find(R, st.l, L, st.sig, st.up, GroupLanes{gl, lg, gmask});
             if (h == kNoIdx) h = st.l;  // cannot happen (the bound came from these bits); x is NaN then
         }
     }
@@ -280,7 +301,7 @@ __global__ __launch_bounds__(256) void k_plain(Problem P) {
         make_line(L, ax, ay, b);
         float hi = __builtin_huge_valf(), lo = -__builtin_huge_valf(), chk = 0.0f;
         for (int h = 0; h < i; ++h) work_unit(R.x(h), R.y(h), R.c(h), L, hi, lo, chk);
-        settle_1dlp<false>(st, R, i, flag_rerun(hi, chk), lo, L, cx, cy, 0, 0, me);
+        settle_1dlp<false>(st, R, i, flag_rerun(hi, chk), lo, L, cx, cy, GroupLanes{0, 0, me});
     }
     for (++i; i < m && !bad; ++i) bad = !finite3(R.x(i), R.y(i), R.c(i));
     if (bad) set_dead(st, kInvalid);
@@ -288,25 +309,86 @@ __global__ __launch_bounds__(256) void k_plain(Problem P) {
     if (st.kind == kPoint) {
         Line L;
         make_line(L, R.x(st.l), R.y(st.l), R.c(st.l));
-        h = group_find(R, st.l, L, st.sig, st.up, 0, 0);
+        h = group_find(R, st.l, L, st.sig, st.up, GroupLanes{0, 0, me});
         if (h == kNoIdx) h = st.l;  // cannot happen (the bound came from these bits); x is NaN then
     }
     finish_lp(P, lp, start, st, h, n1d);
+}
+
+// Reduce the bounds of a fast 1D-LP pass over the group and settle the 1D LP.
+// Only the bound the objective climbs towards is reduced (u_right when c
+// prefers +u, otherwise u_left, taken as the minimum of -u_left), with one
+// butterfly; whether the other side crosses it or comes within FP32 noise of
+// it is decided by one ballot over the lanes' own opposite bounds (the lane
+// holding the opposite extreme flags whenever the full test would).  A
+// flagged 1D LP, or one whose fast pass needs the careful rerun (a lane's
+// position sum is not finite), reduces the other side too and settles as
+// settle_1dlp does; every outcome equals the two-sided reduction's.
+template <bool EXACT, class Rows>
+__device__ __forceinline__ void settle_group(LpState& st, const Rows& R, int v, float hi, float lo, float chk,
+                                             const Line& L, float cx, float cy, const GroupLanes& ln) {
+    const float ninf = -__builtin_huge_valf();
+    const bool up = prefers_up(L, cx, cy);
+    const float r = ln.min(__builtin_isfinite(chk) ? (up ? hi : -lo) : ninf);
+    const float opp = up ? lo : -hi;
+    const bool flag = r == ninf || (!__builtin_isinf(r) && !__builtin_isinf(opp) && (opp > r || near_tie(L, r, opp)));
+    if (!ln.any(flag)) {
+        move_to(st, v, L, up ? r : -r, up);
+        return;
+    }
+    const float og = ln.max(opp);
+    const float hg = r == ninf ? ninf : (up ? r : -og);
+    const float lgb = up ? og : -r;
+    settle_1dlp<EXACT>(st, R, v, hg, lgb, L, cx, cy, ln);
+}
+
+// The rows of one scan chunk a lane holds: rows c0 + gl + k G, k < SR.
+template <int SR>
+struct Chunk {
+    float x[SR], y[SR], c[SR];
+};
+
+// Load chunk c0 (m >= 1): rows past the LP's end repeat row m - 1, so every
+// load is in range and none needs a branch; they are never tested.
+template <int SR, class Rows>
+__device__ __forceinline__ void load_chunk(Chunk<SR>& ch, const Rows& R, int c0, int gl, int G, int m) {
+#pragma unroll
+    for (int k = 0; k < SR; ++k) {
+        int idx = c0 + gl + k * G;
+        idx = idx < m ? idx : m - 1;
+        ch.x[k] = R.x(idx);
+        ch.y[k] = R.y(idx);
+        ch.c[k] = R.c(idx);
+    }
 }
 
 // Solve the LP `lp` (-1: none) with a group of G = 2^lg lanes; every lane of
 // the wave calls this together, each group with its own LP.  LGC >= 0 fixes
 // lg at compile time; LGC = -1 takes it from lg_rt (one body for any width,
 // which keeps the persistent kernel's register count at one width's).
-// A scan step tests SR rows per lane (a window of SR G rows, loads issued
-// together); a 1D LP longer than two group widths folds U work units per
-// lane per step (U a multiple of 4, loads issued together).  More of either
-// means fewer dependent memory round trips per LP and more registers.
-template <int LGC, bool WIDE, bool EXACT = false, int SR = 1, int U = 4>
-__device__ __forceinline__ void solve_group(const Problem& P, int64_t lp, int lg_rt = 0) {
+//
+// The scan (Sec. 2.1, outcome (1) or (2) per row) walks the LP in chunks of
+// SR G rows held in registers, SR rows per lane; a chunk's rows are checked
+// for non-finite values once, when it arrives.  The first violated row of the
+// chunk is found by ballots; after its 1D LP the rest of the same chunk is
+// tested again from the registers, so a violation costs no reload.  The 1D LP on
+// row v (Eq. (3)-(4)) takes rows below the chunk from memory, U work units
+// per lane per step with their loads issued together, and the chunk's own
+// rows below v from the registers.
+//
+// With CACHE > 0 the wave keeps the leading rows of its LPs in LDS (`lds`,
+// 3 CACHE floats: x, y and c, each split evenly between the wave's groups,
+// so a group keeps its LP's first CACHE G / 64 rows).  The rows are stored
+// when their chunk arrives, and 1D LPs read them from LDS: most re-reads fall
+// on the leading rows (Seidel's order makes row h's expected re-reads about
+// 2 ln(m / h)).  Only the wave's own lanes touch its part of LDS, and the LDS
+// executes one wave's accesses in order, so no barrier is needed.
+template <int LGC, bool WIDE, bool EXACT = false, int SR = 1, int U = 4, int CACHE = 0>
+__device__ __forceinline__ void solve_group(const Problem& P, int64_t lp, int lg_rt = 0, float* lds = nullptr) {
     static_assert(SR >= 1 && U >= 4 && U % 4 == 0, "scan rows and work units per lane");
     const int lg = LGC >= 0 ? LGC : lg_rt;
     const int G = 1 << lg;
+    const int C = SR * G;  // rows per chunk
     const int lane = __lane_id();
     const int gl = lane & (G - 1);
     const int gbase = lane & ~(G - 1);
@@ -327,61 +409,100 @@ __device__ __forceinline__ void solve_group(const Problem& P, int64_t lp, int lg
     init_state(st, cx, cy);
     if (lp >= 0 && !ok) set_dead(st, kInvalid);
     bool done = lp < 0 || !ok || m == 0;
-    bool bad = false;
-    int cur = 0;
     int n1d = 0;
+    int cs = 0;          // first row of the current chunk
+    int pos = 0;         // rows below pos are settled
+    bool fresh = true;   // the current chunk has not been checked yet
+    Chunk<SR> cur;
+    if (!done) load_chunk(cur, R, 0, gl, G, m);
+    // this group's rows in LDS: rows [0, rg) of its LP
+    const int rg = CACHE >> (6 - lg);
+    float* const kx = CACHE ? lds + (lane >> lg) * rg : nullptr;
+    float* const ky = CACHE ? kx + CACHE : nullptr;
+    float* const kc = CACHE ? kx + 2 * CACHE : nullptr;
 
     while (__ballot(!done) != 0) {
-        // scan window: rows cur + gl + k G, k < SR
-        float tx[SR], ty[SR], tb[SR];
-        bool in[SR];
+        if (fresh && !done) {  // a non-finite row anywhere makes the LP INVALID
+            bool nf = false;
 #pragma unroll
-        for (int k = 0; k < SR; ++k) {
-            int idx = cur + gl + k * G;
-            in[k] = !done && idx < m;
-            tx[k] = ty[k] = tb[k] = 0.0f;
-            if (in[k]) {
-                tx[k] = R.x(idx);
-                ty[k] = R.y(idx);
-                tb[k] = R.c(idx);
+            for (int k = 0; k < SR; ++k) nf |= cs + gl + k * G < m && !finite3(cur.x[k], cur.y[k], cur.c[k]);
+            if ((__ballot(nf) & gmask) != 0) {
+                set_dead(st, kInvalid);
+                done = true;
+            }
+            if constexpr (CACHE > 0) {
+#pragma unroll
+                for (int k = 0; k < SR; ++k) {
+                    const int idx = cs + gl + k * G;
+                    if (idx < rg && idx < m) {
+                        kx[idx] = cur.x[k];
+                        ky[idx] = cur.y[k];
+                        kc[idx] = cur.c[k];
+                    }
+                }
+                wave_lds_order();
             }
         }
-        bool any_np = false;
-#pragma unroll
-        for (int k = 0; k < SR; ++k) any_np |= in[k];
-        const bool all_point = __ballot(any_np && st.kind != kPoint) == 0;
-        // the first violated row of the window: the smallest k with a hit, then
-        // the group's lowest lane
+        fresh = false;
+        // the first violated row at or after pos: the smallest k with a hit,
+        // then the group's lowest lane
         uint64_t bal = 0;
         int ksel = 0;
         float sx = 0.0f, sy = 0.0f, sb = 0.0f;
+        if (__ballot(!done && st.kind != kPoint) == 0) {  // every live LP of the wave is at a vertex
 #pragma unroll
-        for (int k = SR - 1; k >= 0; --k) {
-            bool fin = finite3(tx[k], ty[k], tb[k]);
-            bad |= in[k] && !fin;
-            bool viol;
-            if (all_point) viol = in[k] && point_violated(tx[k], ty[k], tb[k], st.px, st.py);
-            else viol = in[k] && fin && row_violates(tx[k], ty[k], tb[k], st);
-            uint64_t bk = __ballot(viol) & gmask;
-            if (bk != 0) {
-                bal = bk;
-                ksel = k;
-                sx = tx[k];
-                sy = ty[k];
-                sb = tb[k];
+            for (int k = SR - 1; k >= 0; --k) {
+                const int idx = cs + gl + k * G;
+                const bool viol = !done && idx >= pos && idx < m &&
+                                  point_violated(cur.x[k], cur.y[k], cur.c[k], st.px, st.py);
+                const uint64_t bk = __ballot(viol) & gmask;
+                if (bk != 0) {
+                    bal = bk;
+                    ksel = k;
+                    sx = cur.x[k];
+                    sy = cur.y[k];
+                    sb = cur.c[k];
+                }
+            }
+        } else {
+#pragma unroll
+            for (int k = SR - 1; k >= 0; --k) {
+                const int idx = cs + gl + k * G;
+                const bool viol = !done && idx >= pos && idx < m && row_violates(cur.x[k], cur.y[k], cur.c[k], st);
+                const uint64_t bk = __ballot(viol) & gmask;
+                if (bk != 0) {
+                    bal = bk;
+                    ksel = k;
+                    sx = cur.x[k];
+                    sy = cur.y[k];
+                    sb = cur.c[k];
+                }
             }
         }
         if (bal == 0) {
-            if (!done) {
-                cur += SR * G;
-                if (cur >= m) done = true;
+            if (!done) {  // next chunk
+                cs += C;
+                pos = cs;
+                if (cs >= m) {
+                    done = true;
+                } else {
+                    load_chunk(cur, R, cs, gl, G, m);
+                    fresh = true;
+                }
             }
         } else {
-            int src = __builtin_ctzll(bal);
-            int v = cur + ksel * G + (src - gbase);
-            float lx = __shfl(sx, src);
-            float ly = __shfl(sy, src);
-            float lb = __shfl(sb, src);
+            const int src = __builtin_ctzll(bal);
+            const int v = cs + ksel * G + (src - gbase);
+            float lx, ly, lb;
+            if constexpr (LGC == 6) {  // one group per wave: src is wave-uniform
+                lx = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, sx), src));
+                ly = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, sy), src));
+                lb = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, sb), src));
+            } else {
+                lx = __shfl(sx, src);
+                ly = __shfl(sy, src);
+                lb = __shfl(sb, src);
+            }
             if (lx == 0.0f && ly == 0.0f) {  // 0 <= b with b < 0
                 set_dead(st, kInfeasible);
             } else {
@@ -389,12 +510,49 @@ __device__ __forceinline__ void solve_group(const Problem& P, int64_t lp, int lg
                 Line L;
                 make_line(L, lx, ly, lb);
                 float hi = __builtin_huge_valf(), lo = -__builtin_huge_valf(), chk = 0.0f;
-                if (v > 2 * G) {  // long 1D LPs: U units per lane per step, loads issued together
-                    for (int h = gl; h < v; h += U * G) {
+                // rows below the chunk: the leading ones from LDS, the rest from memory
+                int from = 0;
+                if constexpr (CACHE > 0) {
+                    from = cs < rg ? cs : rg;
+                    for (int h = gl; h < from; h += U * G) {
                         float x[U], y[U], c[U];
 #pragma unroll
                         for (int k = 0; k < U; ++k) {
-                            int hk = h + k * G < v ? h + k * G : v - 1;
+                            int hk = h + k * G;
+                            hk = hk < from ? hk : from - 1;
+                            x[k] = kx[hk];
+                            y[k] = ky[hk];
+                            c[k] = kc[hk];
+                        }
+#pragma unroll
+                        for (int k = 0; k < U; k += 4)
+                            work_units4(*reinterpret_cast<const float(*)[4]>(x + k),
+                                        *reinterpret_cast<const float(*)[4]>(y + k),
+                                        *reinterpret_cast<const float(*)[4]>(c + k), L, hi, lo, chk);
+                    }
+                    for (int h = from + gl; h < cs; h += U * G) {
+                        float x[U], y[U], c[U];
+#pragma unroll
+                        for (int k = 0; k < U; ++k) {
+                            int hk = h + k * G;
+                            hk = hk < cs ? hk : cs - 1;
+                            x[k] = R.x(hk);
+                            y[k] = R.y(hk);
+                            c[k] = R.c(hk);
+                        }
+#pragma unroll
+                        for (int k = 0; k < U; k += 4)
+                            work_units4(*reinterpret_cast<const float(*)[4]>(x + k),
+                                        *reinterpret_cast<const float(*)[4]>(y + k),
+                                        *reinterpret_cast<const float(*)[4]>(c + k), L, hi, lo, chk);
+                    }
+                } else if (cs > 2 * G) {
+                    for (int h = gl; h < cs; h += U * G) {
+                        float x[U], y[U], c[U];
+#pragma unroll
+                        for (int k = 0; k < U; ++k) {
+                            int hk = h + k * G;
+                            if constexpr (SR % U != 0) hk = hk < cs ? hk : cs - 1;
                             x[k] = R.x(hk);
                             y[k] = R.y(hk);
                             c[k] = R.c(hk);
@@ -406,21 +564,37 @@ __device__ __forceinline__ void solve_group(const Problem& P, int64_t lp, int lg
                                         *reinterpret_cast<const float(*)[4]>(c + k), L, hi, lo, chk);
                     }
                 } else {
-                    for (int h = gl; h < v; h += G) work_unit(R.x(h), R.y(h), R.c(h), L, hi, lo, chk);
+                    for (int h = gl; h < cs; h += G) work_unit(R.x(h), R.y(h), R.c(h), L, hi, lo, chk);
                 }
-                hi = group_min(flag_rerun(hi, chk), lg);
-                lo = group_max(lo, lg);
-                settle_1dlp<EXACT>(st, R, v, hi, lo, L, cx, cy, gl, lg, gmask);
+                // the chunk's rows below v, from the registers
+#pragma unroll
+                for (int k = 0; k < SR; ++k)
+                    if (cs + gl + k * G < v) work_unit(cur.x[k], cur.y[k], cur.c[k], L, hi, lo, chk);
+                settle_group<EXACT>(st, R, v, hi, lo, chk, L, cx, cy, GroupLanes{gl, lg, gmask});
             }
-            cur = v + 1;
-            if (cur >= m || st.kind == kDead) done = true;
+            pos = v + 1;
+            if (pos >= m || st.kind == kDead) done = true;
         }
     }
-    finish_group(P, lp, start, R, st, cur, m, bad, n1d, gl, lg, gmask);
+    // rows of later chunks are checked for non-finite values by finish_group
+    finish_group(P, lp, start, R, st, cs + C < m ? cs + C : m, m, false, n1d, gl, lg, gmask);
 }
 
-// Eight waves per SIMD (at most 64 VGPRs): the scan and the work units wait
-// on memory, and more waves hide more of it.
+// Scan rows per lane by group width 2^lg: a 64-lane group tests 256 rows per
+// chunk, 16- and 32-lane groups two rows per lane, narrower groups one (more
+// rows per lane cut the scan's instructions per row; narrow groups violate
+// too often in a chunk for that to pay).
+constexpr int scan_rows(int lg) { return lg >= 6 ? 4 : lg >= 4 ? 2 : 1; }
+
+// Rows of LP kept in LDS per wave (split between its groups) by the group,
+// binned and persistent kernels: 3 x 4 B per row, four waves per workgroup,
+// sized so that eight (group) or seven (binned, persistent) workgroups fit
+// the 160 KB of a CU.
+constexpr int kCacheGroup = 384;
+constexpr int kCacheBinned = 448;
+
+// Eight waves per SIMD (at most 64 VGPRs, a few spilled at G >= 16): the
+// scan and the work units wait on memory, and more waves hide more of it.
 template <int G, bool WIDE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_group(Problem P) {
     constexpr int LPS_PER_BLOCK = 256 / G;
@@ -428,7 +602,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
     int64_t lp = -1;
     if (q < P.num_lps) lp = P.order ? (int64_t)P.order[q] : q;
     constexpr int LG = G == 4 ? 2 : G == 8 ? 3 : G == 16 ? 4 : G == 32 ? 5 : 6;
-    solve_group<LG, WIDE>(P, lp);
+    __shared__ float cache[4][kCacheGroup ? 3 * kCacheGroup : 1];
+    solve_group<LG, WIDE, false, scan_rows(LG), 4, kCacheGroup>(P, lp, 0, cache[threadIdx.x >> 6]);
 }
 
 // Fix-up pass after every solve: each wave looks at 64 statuses and solves
@@ -466,10 +641,6 @@ __device__ __forceinline__ int fkey(float f) {
     return k ^ ((k >> 31) & 0x7fffffff);
 }
 __device__ __forceinline__ float funkey(int k) { return __builtin_bit_cast(float, k ^ ((k >> 31) & 0x7fffffff)); }
-
-// Compiler-level ordering of LDS accesses between lanes of one wave (the LDS
-// executes one wave's instructions in order).
-__device__ __forceinline__ void wave_lds_order() { __atomic_signal_fence(__ATOMIC_SEQ_CST); }
 
 // One waiting group's 1D LP, as published to the wave.
 struct alignas(16) PoolRec {
@@ -690,7 +861,7 @@ __device__ __forceinline__ void solve_pool(const Problem& P, int64_t lp, int lg_
                 set_dead(st, kInfeasible);
             } else {
                 float hi = funkey(S.g[grp].hi), lo = funkey(S.g[grp].lo);
-                settle_1dlp<false>(st, R, v, hi, lo, L, cx, cy, gl, lg, gmask);
+                settle_1dlp<false>(st, R, v, hi, lo, L, cx, cy, GroupLanes{gl, lg, gmask});
             }
             cur = v + 1;
             if (cur >= m || st.kind == kDead) done = true;
@@ -771,27 +942,37 @@ __global__ __launch_bounds__(kBinBlocks) void k_scan(Workspace W, PersistPlan pl
         src ^= 1;
         __syncthreads();
     }
+    // queue order: the wide classes, then the others, each part largest
+    // class first
     int base = 0;
-    for (int c = kClasses - 1; c >= 0; --c) {
-        int incl = s[src][c][t];
-        W.blocks[t * kClasses + c] = base + incl - own[c];
-        base += s[src][c][kBinBlocks - 1];
-    }
+    for (int pass = 0; pass < 2; ++pass)
+        for (int c = kClasses - 1; c >= 0; --c) {
+            if ((plan.log2_lanes[c] == kWideLg) != (pass == 0)) continue;
+            int incl = s[src][c][t];
+            W.blocks[t * kClasses + c] = base + incl - own[c];
+            base += s[src][c][kBinBlocks - 1];
+        }
     if (t == 0) {
         QueueHeader* Q = W.q;
-        int e = 0, sb = 0;
-        for (int j = 0; j < kClasses; ++j) {  // queue order: largest class first
-            int c = kClasses - 1 - j;
-            int n = s[src][c][kBinBlocks - 1];
-            int lg = plan.log2_lanes[c];
-            Q->e_start[j] = e;
-            Q->e_end[j] = e + n;
-            Q->lg[j] = lg;
-            sb += (n + (64 >> lg) - 1) >> (6 - lg);
-            Q->sb_end[j] = sb;
-            e += n;
-        }
+        int e = 0, sb = 0, j = 0, nw = 0;
+        for (int pass = 0; pass < 2; ++pass)
+            for (int c = kClasses - 1; c >= 0; --c) {
+                const bool wide = plan.log2_lanes[c] == kWideLg;
+                if (wide != (pass == 0)) continue;
+                int n = s[src][c][kBinBlocks - 1];
+                int lg = plan.log2_lanes[c];
+                Q->e_start[j] = e;
+                Q->e_end[j] = e + n;
+                Q->lg[j] = lg;
+                if (wide) nw += n;  // no sub-batches: the wide kernel takes them
+                else sb += (n + (64 >> lg) - 1) >> (6 - lg);
+                Q->sb_end[j] = sb;
+                e += n;
+                ++j;
+            }
         Q->num_sb = sb;
+        Q->n_wide = nw;
+        Q->wide_head = 0;
         int dyn = (int)(((int64_t)sb * plan.dyn_frac_1024) >> 10);
         Q->dyn_begin = sb - dyn;
         for (int x = 0; x < kQueues; ++x) W.heads[x * kHeadStride] = 0;
@@ -822,14 +1003,14 @@ __device__ __forceinline__ int sub_batch_slot(const QueueHeader& Q, int k) {
 // G = 2^lg with lg = Q.lg[j] (fixed at compile time when LGC >= 0).
 template <int LGC, bool WIDE>
 __device__ __forceinline__ void run_sub_batch(const Problem& P, const Workspace& W, const QueueHeader& Q, int k,
-                                              int j) {
+                                              int j, float* lds) {
     const int lg = LGC >= 0 ? LGC : Q.lg[j];
     int sb0 = j ? Q.sb_end[j - 1] : 0;
     int first = Q.e_start[j] + ((k - sb0) << (6 - lg));
     int q = first + (__lane_id() >> lg);
     int64_t lp = q < Q.e_end[j] ? (int64_t)W.order[q] : -1;
     if (lp >= P.num_lps) lp = -1;  // never read outside the batch, whatever the queue holds
-    solve_group<LGC, WIDE>(P, lp, lg);
+    solve_group<LGC, WIDE, false, LGC >= 0 ? scan_rows(LGC) : 1, 4, kCacheBinned>(P, lp, lg, lds);
 }
 
 __device__ __forceinline__ void load_header(QueueHeader& Qs, const Workspace& W) {
@@ -852,11 +1033,13 @@ template <bool WIDE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) void k_persist(Problem P, Workspace W,
                                                                                          PersistPlan plan) {
     __shared__ QueueHeader Qs;
+    __shared__ float cache[4][kCacheBinned ? 3 * kCacheBinned : 1];
+    float* const lds = cache[threadIdx.x >> 6];
     load_header(Qs, W);
     const QueueHeader& Q = Qs;
     const int waves = (int)(gridDim.x * (blockDim.x >> 6));
     const int wid = (int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
-    for (int k = wid; k < Q.dyn_begin; k += waves) run_sub_batch<-1, WIDE>(P, W, Q, k, sub_batch_slot(Q, k));
+    for (int k = wid; k < Q.dyn_begin; k += waves) run_sub_batch<-1, WIDE>(P, W, Q, k, sub_batch_slot(Q, k), lds);
     const int chunk = plan.chunk > 0 ? plan.chunk : 1;
     const int ndyn = Q.num_sb - Q.dyn_begin;
     for (int t = 0; t < kQueues; ++t) {
@@ -870,7 +1053,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) void k
             int i1 = min(i0 + chunk, len);
             for (int i = i0; i < i1; ++i) {
                 int k = Q.dyn_begin + x + i * kQueues;
-                run_sub_batch<-1, WIDE>(P, W, Q, k, sub_batch_slot(Q, k));
+                run_sub_batch<-1, WIDE>(P, W, Q, k, sub_batch_slot(Q, k), lds);
             }
         }
     }
@@ -878,21 +1061,304 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) void k
 
 // Binned, non-persistent: one wave per sub-batch in queue order (largest LPs
 // first); the grid is an upper bound and surplus waves exit at once.  The
-// hardware dispatcher starts a new wave wherever one finishes.  Eight waves
-// per SIMD (at most 64 VGPRs, nothing spilled).
+// hardware dispatcher starts a new wave wherever one finishes.  Seven waves
+// per SIMD (at most 72 VGPRs): at eight the widest class's chunk registers
+// spill.
 template <bool WIDE>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_binned(Problem P, Workspace W) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) void k_binned(Problem P, Workspace W) {
     __shared__ QueueHeader Qs;
+    __shared__ float cache[4][kCacheBinned ? 3 * kCacheBinned : 1];
+    float* const lds = cache[threadIdx.x >> 6];
     load_header(Qs, W);
     const int k = (int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
     if (k >= Qs.num_sb) return;
     int j = sub_batch_slot(Qs, k);
     switch (Qs.lg[j]) {
-        case 2: run_sub_batch<2, WIDE>(P, W, Qs, k, j); break;
-        case 3: run_sub_batch<3, WIDE>(P, W, Qs, k, j); break;
-        case 4: run_sub_batch<4, WIDE>(P, W, Qs, k, j); break;
-        case 5: run_sub_batch<5, WIDE>(P, W, Qs, k, j); break;
-        default: run_sub_batch<6, WIDE>(P, W, Qs, k, j); break;
+        case 2: run_sub_batch<2, WIDE>(P, W, Qs, k, j, lds); break;
+        case 3: run_sub_batch<3, WIDE>(P, W, Qs, k, j, lds); break;
+        case 4: run_sub_batch<4, WIDE>(P, W, Qs, k, j, lds); break;
+        case 5: run_sub_batch<5, WIDE>(P, W, Qs, k, j, lds); break;
+        default: run_sub_batch<6, WIDE>(P, W, Qs, k, j, lds); break;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// wide: one workgroup of two waves per LP, its leading rows kept in LDS
+// ---------------------------------------------------------------------------
+// The multi-wave form of the work-unit scheme (Sec. 3, Fig. NewWork: the work
+// units of a 1D LP shared by all threads of a block): 128 lanes scan a chunk
+// of 128 kWideRows rows of one LP at once and share each 1D LP's work units.
+// As the scan passes them, the LP's first kWideCache rows are stored in LDS,
+// so the 1D LPs, which re-read every earlier row (Eq. (3)-(4)), read those
+// from LDS instead of the cache hierarchy; Seidel's re-reads fall mostly on
+// the leading rows (row h is re-read about 2 ln(m / h) times).  The waves
+// combine values through an LDS exchange: each wave posts one record, a
+// barrier, and every thread reads all records.  Every wave keeps its own copy
+// of the LP state and takes the same decisions on the same exchanged values,
+// so the state itself is never exchanged.  The FP64 pass of an overflowing 1D
+// LP is left to the fix-up kernel (kDeferred).
+//
+// Measured on MI355X it is slower than one wave per LP for every size class
+// (the exchanges put a barrier on each chunk and each 1D LP of a chain that
+// is already latency-bound; more waves per LP and larger chunks were slower
+// still), so the tuner only picks it where it wins; the shape kept is the
+// fastest one measured.
+constexpr int kWideWaves = 2;
+constexpr int kWideThreads = 64 * kWideWaves;
+constexpr int kWideCache = 1650;  // rows of an LP kept in LDS (19.9 KB: eight workgroups fit a CU)
+constexpr int kWideRows = 4;      // rows per lane in a scan chunk
+
+struct WideLds {
+    float x[kWideCache], y[kWideCache], c[kWideCache];
+    float xc[2][kWideWaves][4];  // exchange records, two sets used in turn
+};
+
+// The workgroup as the cooperating lanes of the 1D-LP helpers.  A wave can be
+// at most one exchange ahead of another (it cannot pass the next barrier
+// alone), so a record set is rewritten only after every wave has read it.
+struct WideLanes {
+    WideLds* S;
+    int t;            // thread in the workgroup
+    mutable int par;  // record set of the next exchange (the same in every wave)
+    __device__ __forceinline__ int first() const { return t; }
+    __device__ __forceinline__ int step() const { return kWideThreads; }
+    // post this wave's record (wave-uniform values), wait for every wave's
+    __device__ __forceinline__ const float (*post(float a, float b, float c, float d) const)[4] {
+        if (__lane_id() == 0) {
+            float* p = S->xc[par][t >> 6];
+            p[0] = a;
+            p[1] = b;
+            p[2] = c;
+            p[3] = d;
+        }
+        __syncthreads();
+        const float(*r)[4] = S->xc[par];
+        par ^= 1;
+        return r;
+    }
+    __device__ __forceinline__ float min(float v) const {
+        const float(*r)[4] = post(group_min(v, 6), 0.0f, 0.0f, 0.0f);
+        float m = r[0][0];
+#pragma unroll
+        for (int j = 1; j < kWideWaves; ++j) m = fmin_(m, r[j][0]);
+        return m;
+    }
+    __device__ __forceinline__ float max(float v) const {
+        const float(*r)[4] = post(group_max(v, 6), 0.0f, 0.0f, 0.0f);
+        float m = r[0][0];
+#pragma unroll
+        for (int j = 1; j < kWideWaves; ++j) m = fmax_(m, r[j][0]);
+        return m;
+    }
+    __device__ __forceinline__ int imin(int v) const {
+        const float(*r)[4] = post(__builtin_bit_cast(float, group_min_i(v, 6)), 0.0f, 0.0f, 0.0f);
+        int m = __builtin_bit_cast(int, r[0][0]);
+#pragma unroll
+        for (int j = 1; j < kWideWaves; ++j) m = imin_(m, __builtin_bit_cast(int, r[j][0]));
+        return m;
+    }
+    __device__ __forceinline__ bool any(bool b) const {
+        const float(*r)[4] = post(__ballot(b) != 0 ? 1.0f : 0.0f, 0.0f, 0.0f, 0.0f);
+        float m = r[0][0];
+#pragma unroll
+        for (int j = 1; j < kWideWaves; ++j) m = fmax_(m, r[j][0]);
+        return m != 0.0f;
+    }
+};
+
+// Rows of the LP: the leading kWideCache from LDS, the rest from memory.
+template <bool WIDE>
+struct WideRows {
+    const WideLds* S;
+    RowRef<WIDE> G;
+    __device__ __forceinline__ float x(int h) const { return h < kWideCache ? S->x[h] : G.x(h); }
+    __device__ __forceinline__ float y(int h) const { return h < kWideCache ? S->y[h] : G.y(h); }
+    __device__ __forceinline__ float c(int h) const { return h < kWideCache ? S->c[h] : G.c(h); }
+};
+
+// Fold rows [lo, hi) of the LP into the bounds on line L, four per thread per
+// step with their reads issued together (rows past the end repeat row hi - 1,
+// which cannot change a min or a max).
+template <class Rows>
+__device__ __forceinline__ void wide_units(const Rows& R, int lo, int hi, int t, const Line& L, float& bh, float& bl,
+                                           float& chk) {
+    for (int h = lo + t; h < hi; h += 4 * kWideThreads) {
+        float x[4], y[4], c[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            int hk = h + k * kWideThreads;
+            hk = hk < hi ? hk : hi - 1;
+            x[k] = R.x(hk);
+            y[k] = R.y(hk);
+            c[k] = R.c(hk);
+        }
+        work_units4(x, y, c, L, bh, bl, chk);
+    }
+}
+
+// LDS view of rows [0, kWideCache) for the work-unit loop.
+struct LdsRows {
+    const WideLds* S;
+    __device__ __forceinline__ float x(int h) const { return S->x[h]; }
+    __device__ __forceinline__ float y(int h) const { return S->y[h]; }
+    __device__ __forceinline__ float c(int h) const { return S->c[h]; }
+};
+
+// Solve LP `lp` with the whole workgroup (every thread calls this together).
+template <bool WIDE, int SR>
+__device__ __forceinline__ void solve_wide(const Problem& P, int64_t lp, WideLds& S, const WideLanes& ln) {
+    constexpr int C = SR * kWideThreads;  // rows per chunk
+    const int t = ln.t;
+    const int w = t >> 6;
+    int64_t start = 0;
+    int m = 0;
+    const float cx = P.cx[lp], cy = P.cy[lp];
+    const bool ok = lp_range(P, lp, start, m) && __builtin_isfinite(cx) && __builtin_isfinite(cy);
+    const RowRef<WIDE> G{P.ax, P.ay, P.b, (typename std::conditional<WIDE, int64_t, uint32_t>::type)start};
+    const WideRows<WIDE> R{&S, G};
+
+    LpState st;
+    init_state(st, cx, cy);
+    if (!ok) set_dead(st, kInvalid);
+    bool done = !ok || m == 0;
+    int n1d = 0;
+    int cs = 0;         // first row of the current chunk
+    int pos = 0;        // rows below pos are settled
+    bool fresh = true;  // the current chunk has not been checked and stored yet
+    Chunk<SR> cur;      // rows cs + t + k 256
+    if (!done) load_chunk(cur, G, 0, t, kWideThreads, m);
+
+    while (!done) {
+        bool nf = false;
+        if (fresh) {  // check the new rows and keep the leading ones in LDS
+#pragma unroll
+            for (int k = 0; k < SR; ++k) {
+                const int idx = cs + t + k * kWideThreads;
+                if (idx < m) {
+                    nf |= !finite3(cur.x[k], cur.y[k], cur.c[k]);
+                    if (idx < kWideCache) {
+                        S.x[idx] = cur.x[k];
+                        S.y[idx] = cur.y[k];
+                        S.c[idx] = cur.c[k];
+                    }
+                }
+            }
+        }
+        fresh = false;
+        // this wave's first violated row at or after pos (rows are ordered by
+        // k, then wave, then lane), then the workgroup's through the exchange;
+        // a non-finite row anywhere in the chunk posts -1 (INVALID)
+        int wv = kNoIdx;
+        float wx = 0.0f, wy = 0.0f, wb = 0.0f;
+        const bool pt = st.kind == kPoint;
+#pragma unroll
+        for (int k = 0; k < SR; ++k) {
+            const int idx = cs + t + k * kWideThreads;
+            const bool viol = idx >= pos && idx < m &&
+                              (pt ? point_violated(cur.x[k], cur.y[k], cur.c[k], st.px, st.py)
+                                  : row_violates(cur.x[k], cur.y[k], cur.c[k], st));
+            const uint64_t b = __ballot(viol);
+            if (b != 0 && wv == kNoIdx) {
+                const int src = __builtin_ctzll(b);
+                wv = cs + k * kWideThreads + w * 64 + src;
+                wx = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, cur.x[k]), src));
+                wy = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, cur.y[k]), src));
+                wb = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, cur.c[k]), src));
+            }
+        }
+        if (__ballot(nf) != 0) wv = -1;
+        const float(*r)[4] = ln.post(__builtin_bit_cast(float, wv), wx, wy, wb);
+        int v = __builtin_bit_cast(int, r[0][0]), vj = 0;
+#pragma unroll
+        for (int j = 1; j < kWideWaves; ++j) {
+            const int vk = __builtin_bit_cast(int, r[j][0]);
+            if (vk < v) {
+                v = vk;
+                vj = j;
+            }
+        }
+        if (v == -1) {
+            set_dead(st, kInvalid);
+            done = true;
+        } else if (v == kNoIdx) {  // next chunk
+            cs += C;
+            pos = cs;
+            if (cs >= m) {
+                done = true;
+            } else {
+                load_chunk(cur, G, cs, t, kWideThreads, m);
+                fresh = true;
+            }
+        } else {
+            const float lx = r[vj][1], ly = r[vj][2], lb = r[vj][3];
+            if (lx == 0.0f && ly == 0.0f) {  // 0 <= b with b < 0
+                set_dead(st, kInfeasible);
+            } else {
+                ++n1d;
+                Line L;
+                make_line(L, lx, ly, lb);
+                float hi = __builtin_huge_valf(), lo = -__builtin_huge_valf(), chk = 0.0f;
+                const int vl = v < kWideCache ? v : kWideCache;
+                wide_units(LdsRows{&S}, 0, vl, t, L, hi, lo, chk);
+                if (v > kWideCache) wide_units(G, kWideCache, v, t, L, hi, lo, chk);
+                // both sides in one exchange: the bound c climbs towards (as a
+                // minimum) and the other one (as a maximum of its negation)
+                const bool up = prefers_up(L, cx, cy);
+                const float ninf = -__builtin_huge_valf();
+                const float sel = __builtin_isfinite(chk) ? (up ? hi : -lo) : ninf;
+                const float opp = up ? lo : -hi;
+                const float(*e)[4] = ln.post(group_min(sel, 6), group_max(opp, 6), 0.0f, 0.0f);
+                float rs = e[0][0], ro = e[0][1];
+#pragma unroll
+                for (int j = 1; j < kWideWaves; ++j) {
+                    rs = fmin_(rs, e[j][0]);
+                    ro = fmax_(ro, e[j][1]);
+                }
+                const float hg = rs == ninf ? ninf : (up ? rs : -ro);
+                const float lgb = up ? ro : -rs;
+                settle_1dlp<false>(st, R, v, hg, lgb, L, cx, cy, ln);
+            }
+            pos = v + 1;
+            if (pos >= m || st.kind == kDead) done = true;
+        }
+    }
+    // an LP that died infeasible: the rows after the last chunk may still hold
+    // a non-finite value (INVALID)
+    if (st.kind == kDead && st.dead_status == kInfeasible) {
+        bool bad = false;
+        for (int idx = (cs + C < m ? cs + C : m) + t; idx < m; idx += kWideThreads)
+            bad |= !finite3(G.x(idx), G.y(idx), G.c(idx));
+        if (ln.any(bad)) set_dead(st, kInvalid);
+    }
+    int h = -1;
+    if (st.kind == kPoint) {
+        Line L;
+        make_line(L, R.x(st.l), R.y(st.l), R.c(st.l));
+        h = group_find(R, st.l, L, st.sig, st.up, ln);
+        if (h == kNoIdx) h = st.l;  // cannot happen (the bound came from these bits); x is NaN then
+    }
+    if (t == 0) finish_lp(P, lp, start, st, h, n1d);
+}
+
+// Entries [0, n_wide) of the queue (the wide classes, largest first), one LP
+// per workgroup at a time, taken from the queue's wide head.  The LDS rows
+// (20 KB a workgroup) allow eight workgroups per CU.
+template <bool WIDE>
+__global__ __launch_bounds__(kWideThreads) void k_wide(Problem P, Workspace W) {
+    __shared__ WideLds S;
+    __shared__ int next;
+    const int t = threadIdx.x;
+    const int n = W.q->n_wide;
+    WideLanes ln{&S, t, 0};
+    while (true) {
+        if (t == 0) next = atomicAdd(&W.q->wide_head, 1);
+        __syncthreads();
+        const int q = next;
+        __syncthreads();  // everyone has read `next` before it is written again
+        if (q >= n) break;
+        int64_t lp = W.order[q];
+        if (lp < 0 || lp >= P.num_lps) continue;  // never read outside the batch, whatever the queue holds
+        solve_wide<WIDE, kWideRows>(P, lp, S, ln);
     }
 }
 
@@ -932,14 +1398,20 @@ bool group_supported(int g) {
     return g == 4 || g == 8 || g == 16 || g == 32 || g == 64;
 }
 
-hipError_t launch_persistent(const Problem& P, const Workspace& W, const PersistPlan& plan, int grid, bool binned,
-                             hipStream_t stream, hipEvent_t ev_begin, hipEvent_t ev_end) {
+hipError_t launch_persistent(const Problem& P, const Workspace& W, const PersistPlan& plan, int grid, int wide_grid,
+                             bool binned, hipStream_t stream, hipEvent_t ev_begin, hipEvent_t ev_end) {
     if (P.num_lps == 0) return hipSuccess;
     hipLaunchKernelGGL(k_bin, dim3(kBinBlocks), dim3(256), 0, stream, P, W);
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(kBinBlocks), 0, stream, W, plan);
     hipLaunchKernelGGL(k_scatter, dim3(kBinBlocks), dim3(256), 0, stream, P, W);
     if (ev_begin) (void)hipEventRecord(ev_begin, stream);
     const bool wide = wide_rows(P);
+    bool any_wide = false;
+    for (int c = 0; c < kClasses; ++c) any_wide |= plan.log2_lanes[c] == kWideLg;
+    if (any_wide) {
+        if (wide) hipLaunchKernelGGL(k_wide<true>, dim3(wide_grid), dim3(kWideThreads), 0, stream, P, W);
+        else hipLaunchKernelGGL(k_wide<false>, dim3(wide_grid), dim3(kWideThreads), 0, stream, P, W);
+    }
     if (binned) {
         // at most one sub-batch per LP plus one partial sub-batch per class
         int64_t max_sb = P.num_lps + kClasses;
@@ -954,6 +1426,12 @@ hipError_t launch_persistent(const Problem& P, const Workspace& W, const Persist
     if (e == hipSuccess) e = launch_fixup(P, stream);
     if (ev_end) (void)hipEventRecord(ev_end, stream);
     return e;
+}
+
+int wide_blocks_per_cu() {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_wide<false>, kWideThreads, 0) != hipSuccess) return 1;
+    return n > 0 ? n : 1;
 }
 
 int persist_blocks_per_cu() {

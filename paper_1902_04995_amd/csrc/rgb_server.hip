@@ -10,13 +10,11 @@
 //
 // Both copies are kernels on the slot's stream that read and write the
 // pinned buffers directly, not DMA-engine copies: the copies, the solve and
-// the completion event then sit in one in-order queue.  With DMA copies the
-// polled event (and a stream synchronisation) sometimes reported completion
-// before the results had landed in pinned memory -- a request read back
-// zeros -- once the process had many streams sharing the hardware queues.
-// The pinned buffers are fine-grained (coherent) host memory, so the GPU
-// reads a reused ring span as the host last wrote it and its result stores
-// are visible to the host when the kernel has finished.
+// the completion event sit in one in-order queue.  The pinned buffers are
+// fine-grained (coherent) host memory, so the GPU reads a reused ring span as
+// the host last wrote it and its result stores are visible to the host when
+// the kernel has finished.  The slots' streams are non-blocking, so nothing
+// the server's solves depend on may be issued to the null stream.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

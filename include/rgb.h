@@ -175,6 +175,27 @@ rgb_err_t rgb_solve_batch(rgb_ctx_t* ctx, int64_t num_lps, int64_t num_constrain
                           const float* cx, const float* cy, float* x_out, float* y_out,
                           int32_t* status_out, const rgb_solve_opts_t* opts, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * solve as rgb_solve_batch, same arguments, layout, results and errors, but
+ * it allocates nothing.  PERSISTENT and BINNED solves keep their binning and
+ * queue state in a static device array of the library (about 5 MiB, one
+ * copy per device, held until the process ends) instead of a context
+ * workspace; the other families need no workspace.  num_lps is limited to
+ * 2^20 (1,048,576): larger batches return RGB_ERR_TOO_LARGE before anything
+ * is enqueued.  Every call on one device shares that device's array and the
+ * binning kernels of each call rewrite all of the state it reads, so
+ * back-to-back calls need no clearing; calls whose work overlaps on one
+ * device (different streams or host threads without ordering) race on the
+ * array and may return wrong results: order them on one stream.  The
+ * caller passes every input and output buffer as for rgb_solve_batch.
+ * Errors: as rgb_solve_batch (never OOM), TOO_LARGE, and DEVICE if the
+ * array's device address could not be obtained when ctx was created. */
+rgb_err_t rgb_solve_batch_noalloc(rgb_ctx_t* ctx, int64_t num_lps, int64_t num_constraints,
+                                  const int64_t* offsets, const float* ax, const float* ay, const float* b,
+                                  const float* cx, const float* cy, float* x_out, float* y_out,
+                                  int32_t* status_out, const rgb_solve_opts_t* opts, void* stream);
+
 /* Read or replace the configuration AUTO solves on ctx use.  set validates
  * every field (INVALID_ARG otherwise). */
 rgb_err_t rgb_ctx_get_tuning(const rgb_ctx_t* ctx, rgb_tuning_t* out);

@@ -115,6 +115,8 @@ def lib():
         L.rgb_ctx_last_error.restype = ctypes.c_char_p
         L.rgb_solve_batch.argtypes = [P, I64, I64] + [P] * 9 + [ctypes.POINTER(_SolveOpts), P]
         L.rgb_solve_batch.restype = I32
+        L.rgb_solve_batch_noalloc.argtypes = [P, I64, I64] + [P] * 9 + [ctypes.POINTER(_SolveOpts), P]
+        L.rgb_solve_batch_noalloc.restype = I32
         L.rgb_ctx_get_tuning.argtypes = [P, ctypes.POINTER(Tuning)]
         L.rgb_ctx_get_tuning.restype = I32
         L.rgb_ctx_set_tuning.argtypes = [P, ctypes.POINTER(Tuning)]
@@ -299,6 +301,36 @@ def solve_batch(offsets, ax, ay, b, cx, cy, *, variant="auto", lanes_per_lp=0, p
     ctx.check(rc, "rgb_solve_batch")
     if want_n_1dlp:
         return x, y, st, n1d
+    return x, y, st
+
+
+def solve_batch_noalloc(offsets, ax, ay, b, cx, cy, *, out, variant="auto", lanes_per_lp=0, pool_wait=0, chunk=0,
+                        grid=0, queue_share=0, pool_rows=0, stream=None, ctx: Context | None = None, events=None):
+    """rgb_solve_batch_noalloc: the solve of ``solve_batch`` into the caller's
+    ``out=(x, y, status)`` tensors, with no device allocation by the library
+    or by this binding (at most 2^20 LPs; calls that overlap on one device
+    race on the library's static workspace)."""
+    import torch
+    dev = offsets.device
+    if dev.type != "cuda":
+        raise ValueError("solve_batch_noalloc needs CUDA tensors")
+    _check_tensor(offsets, "offsets", torch.int64, dev)
+    for name, t in (("ax", ax), ("ay", ay), ("b", b), ("cx", cx), ("cy", cy)):
+        _check_tensor(t, name, torch.float32, dev)
+    B = offsets.numel() - 1
+    N = ax.numel()
+    if B < 0 or ay.numel() != N or b.numel() != N or cx.numel() != B or cy.numel() != B:
+        raise ValueError("inconsistent batch shapes")
+    _check_out(out, B, dev)
+    x, y, st = out
+    ctx = ctx or context(dev.index or 0)
+    if stream is None:
+        stream = torch.cuda.current_stream(dev)
+    opts = make_opts(variant, lanes_per_lp, pool_wait, chunk, grid, None, events, queue_share, pool_rows)
+    rc = lib().rgb_solve_batch_noalloc(ctx.handle, B, N, _ptr(offsets), _ptr(ax), _ptr(ay), _ptr(b), _ptr(cx),
+                                       _ptr(cy), _ptr(x), _ptr(y), _ptr(st), ctypes.byref(opts),
+                                       ctypes.c_void_p(stream.cuda_stream))
+    ctx.check(rc, "rgb_solve_batch_noalloc")
     return x, y, st
 
 

@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -27,8 +28,24 @@ struct WsSlot {
 
 constexpr int kMaxStreams = 32;
 
+// Workspace of rgb_solve_batch_noalloc: the binning and queue state of one
+// solve of at most kScratchMaxLps LPs, laid out as grow_workspace lays out an
+// allocated one (queue header and heads, per-block class counts, the queue of
+// LP ids, the class per LP).  Every field is written by the binning kernels
+// of the solve that uses it, so nothing needs clearing between calls.
+constexpr int64_t kScratchMaxLps = int64_t(1) << 20;
+constexpr size_t kScratchBlocksAt = 2048;
+constexpr size_t kScratchOrderAt = kScratchBlocksAt + (size_t)rgb::kBinBlocks * rgb::kClasses * 4;
+constexpr size_t kScratchClsAt = kScratchOrderAt + (size_t)kScratchMaxLps * 4;
+constexpr size_t kScratchBytes = kScratchClsAt + (size_t)kScratchMaxLps;
+static_assert(kScratchOrderAt % 256 == 0 && kScratchClsAt % 256 == 0, "scratch layout");
+
 }  // namespace
 
+// One copy per device, held until the process ends.  Host code never uses
+// this name as an address: it takes the device's address from
+// hipGetSymbolAddress (scratch_address below) and passes that to kernels.
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
 struct rgb_ctx {
     int device = 0;
@@ -39,6 +56,7 @@ struct rgb_ctx {
     rgb_tuning_t tuning{};
     std::vector<WsSlot> slots;
     rgb::HostPath* host = nullptr;  // rgb_solve_batch_host state, made on first use
+    void* scratch = nullptr;        // this device's address of `scratch` (null: lookup failed)
     std::string last_error;
 };
 
@@ -180,6 +198,36 @@ rgb_err_t grow_workspace(rgb_ctx_t* ctx, WsSlot& slot, int64_t num_lps) {
     slot.ws.order = reinterpret_cast<int32_t*>(base + order_off);
     slot.ws.cls = reinterpret_cast<uint8_t*>(base + cls_off);
     return RGB_OK;
+}
+
+// Device address of `scratch` on the current device `dev`, looked up once per
+// device (each device holds its own copy at its own address); null if the
+// lookup fails.
+void* scratch_address(int dev) {
+    static std::mutex mu;
+    static std::vector<std::pair<int, void*>> known;
+    std::lock_guard<std::mutex> lk(mu);
+    for (const auto& k : known)
+        if (k.first == dev) return k.second;
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess) {
+        (void)hipGetLastError();  // clear the error so later calls do not report it
+        return nullptr;
+    }
+    known.emplace_back(dev, p);
+    return p;
+}
+
+// The workspace of rgb_solve_batch_noalloc inside the device's `scratch`.
+rgb::Workspace scratch_workspace(void* base_ptr) {
+    char* base = static_cast<char*>(base_ptr);
+    rgb::Workspace w{};
+    w.q = reinterpret_cast<rgb::QueueHeader*>(base);
+    w.heads = reinterpret_cast<int32_t*>(base + 1024);
+    w.blocks = reinterpret_cast<int32_t*>(base + kScratchBlocksAt);
+    w.order = reinterpret_cast<int32_t*>(base + kScratchOrderAt);
+    w.cls = reinterpret_cast<uint8_t*>(base + kScratchClsAt);
+    return w;
 }
 
 // Workspace of the solves issued on `stream`.
@@ -334,6 +382,7 @@ rgb_err_t rgb_ctx_create(int device, const rgb_ctx_opts_t* opts, rgb_ctx_t** out
     ctx->device_key = std::string(prop.name) + " " + arch + " " + std::to_string(prop.multiProcessorCount) + "cu";
     ctx->persist_blocks_per_cu = rgb::persist_blocks_per_cu();
     ctx->wide_blocks_per_cu = rgb::wide_blocks_per_cu();
+    ctx->scratch = scratch_address(device);
     default_tuning(ctx->tuning);
     if (opts && opts->tuning_table) {
         rgb::TableEntry e = table_entry_of(ctx->tuning);
@@ -398,6 +447,35 @@ rgb_err_t rgb_solve_batch(rgb_ctx_t* ctx, int64_t num_lps, int64_t num_constrain
     rgb::Workspace W{};
     if (variant == RGB_VARIANT_PERSISTENT || variant == RGB_VARIANT_BINNED)
         if ((rc = stream_workspace(ctx, stream, num_lps, W)) != RGB_OK) return rc;
+    return enqueue(ctx, make_problem(B, o.n_1dlp_out), variant, cfg, &W, reinterpret_cast<hipStream_t>(stream),
+                   reinterpret_cast<hipEvent_t>(o.ev_begin), reinterpret_cast<hipEvent_t>(o.ev_end));
+}
+
+rgb_err_t rgb_solve_batch_noalloc(rgb_ctx_t* ctx, int64_t num_lps, int64_t num_constraints, const int64_t* offsets,
+                                  const float* ax, const float* ay, const float* b, const float* cx,
+                                  const float* cy, float* x_out, float* y_out, int32_t* status_out,
+                                  const rgb_solve_opts_t* opts, void* stream) {
+    if (!ctx) return RGB_ERR_INVALID_ARG;
+    ctx->last_error.clear();
+    Batch B{num_lps, num_constraints, offsets, ax, ay, b, cx, cy, x_out, y_out, status_out};
+    rgb_err_t rc = check_batch(ctx, B);
+    if (rc != RGB_OK || num_lps == 0) return rc;
+    if (num_lps > kScratchMaxLps)
+        return fail(ctx, RGB_ERR_TOO_LARGE, "rgb_solve_batch_noalloc takes at most %lld LPs, got %lld",
+                    (long long)kScratchMaxLps, (long long)num_lps);
+    rgb_solve_opts_t o{};
+    if (opts) o = *opts;
+    int variant;
+    rgb_tuning_t cfg;
+    if ((rc = resolve(ctx, o, variant, cfg)) != RGB_OK) return rc;
+    DeviceGuard guard(ctx->device);
+    if (!guard.ok) return fail(ctx, RGB_ERR_DEVICE, "cannot select device %d", ctx->device);
+    rgb::Workspace W{};
+    if (variant == RGB_VARIANT_PERSISTENT || variant == RGB_VARIANT_BINNED) {
+        if (!ctx->scratch) return fail(ctx, RGB_ERR_DEVICE, "no address for the static workspace on device %d",
+                                       ctx->device);
+        W = scratch_workspace(ctx->scratch);
+    }
     return enqueue(ctx, make_problem(B, o.n_1dlp_out), variant, cfg, &W, reinterpret_cast<hipStream_t>(stream),
                    reinterpret_cast<hipEvent_t>(o.ev_begin), reinterpret_cast<hipEvent_t>(o.ev_end));
 }

@@ -26,16 +26,16 @@ sys.path.insert(0, ROOT)
 CPU_SAMPLE_S = 10.0  # seconds of oracle work in the cpu_baseline leg
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, public spec
 
-# HBM bytes per launch of the dominant kernel, from rocprofv3 FETCH_SIZE and
+# Fabric bytes per launch of the dominant kernel (the L2's misses, which the
+# last-level MALL cache or HBM serve), from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE passes scaled by the same counters read for a device copy of
 # known size (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0 on gfx950); see profiles/.
 # Keyed by (kernel, workload) and valid only for the kernel sources whose
 # digest is recorded: after any kernel change the figure is reported as null.
 MEASURED_TRAFFIC = {
-    "sources": "6d141b153fb7f381",
-    ('k_group<16>', 'uniform'): 1221830248,
-    ('k_group<8>', 'crowd'): 491983607,
-    ('k_binned', 'uneven'): 9081419069,
+    "sources": "ae1cc0a3adcea1f7",
+    ('k_group<16>', 'uniform'): 888589111,
+    ('k_binned', 'uneven'): 7441264191,
 }
 
 

@@ -1013,6 +1013,21 @@ __device__ __forceinline__ void run_sub_batch(const Problem& P, const Workspace&
     solve_group<LGC, WIDE, false, LGC >= 0 ? scan_rows(LGC) : 1, 4, kCacheBinned>(P, lp, lg, lds);
 }
 
+// Sub-batch k of the queue with the group width of its class fixed at compile
+// time (the same code as the group kernel's for that width).
+template <bool WIDE>
+__device__ __forceinline__ void run_sub_batch_any(const Problem& P, const Workspace& W, const QueueHeader& Q, int k,
+                                                  float* lds) {
+    const int j = sub_batch_slot(Q, k);
+    switch (Q.lg[j]) {
+        case 2: run_sub_batch<2, WIDE>(P, W, Q, k, j, lds); break;
+        case 3: run_sub_batch<3, WIDE>(P, W, Q, k, j, lds); break;
+        case 4: run_sub_batch<4, WIDE>(P, W, Q, k, j, lds); break;
+        case 5: run_sub_batch<5, WIDE>(P, W, Q, k, j, lds); break;
+        default: run_sub_batch<6, WIDE>(P, W, Q, k, j, lds); break;
+    }
+}
+
 __device__ __forceinline__ void load_header(QueueHeader& Qs, const Workspace& W) {
     if (threadIdx.x < sizeof(QueueHeader) / 4)
         reinterpret_cast<int*>(&Qs)[threadIdx.x] = reinterpret_cast<const int*>(W.q)[threadIdx.x];
@@ -1072,14 +1087,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) void k
     load_header(Qs, W);
     const int k = (int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
     if (k >= Qs.num_sb) return;
-    int j = sub_batch_slot(Qs, k);
-    switch (Qs.lg[j]) {
-        case 2: run_sub_batch<2, WIDE>(P, W, Qs, k, j, lds); break;
-        case 3: run_sub_batch<3, WIDE>(P, W, Qs, k, j, lds); break;
-        case 4: run_sub_batch<4, WIDE>(P, W, Qs, k, j, lds); break;
-        case 5: run_sub_batch<5, WIDE>(P, W, Qs, k, j, lds); break;
-        default: run_sub_batch<6, WIDE>(P, W, Qs, k, j, lds); break;
-    }
+    run_sub_batch_any<WIDE>(P, W, Qs, k, lds);
 }
 
 // ---------------------------------------------------------------------------

@@ -581,10 +581,10 @@ __device__ __forceinline__ void solve_group(const Problem& P, int64_t lp, int lg
 }
 
 // Scan rows per lane by group width 2^lg: a 64-lane group tests 256 rows per
-// chunk, 16- and 32-lane groups two rows per lane, narrower groups one (more
-// rows per lane cut the scan's instructions per row; narrow groups violate
-// too often in a chunk for that to pay).
-constexpr int scan_rows(int lg) { return lg >= 6 ? 4 : lg >= 4 ? 2 : 1; }
+// chunk, 8- to 32-lane groups two rows per lane, 4-lane groups one (more rows
+// per lane cut the scan's instructions per row; small LPs violate too often
+// in a chunk for more to pay; measured per width).
+constexpr int scan_rows(int lg) { return lg >= 6 ? 4 : lg >= 3 ? 2 : 1; }
 
 // Rows of LP kept in LDS per wave (split between its groups) by the group,
 // binned and persistent kernels: 3 x 4 B per row, four waves per workgroup,

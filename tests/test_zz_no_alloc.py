@@ -62,3 +62,42 @@ def test_noalloc_rejects_batches_over_the_limit():
         rgb.solve_batch_noalloc(offsets, row[:0], row[:0], row[:0], c, c, out=out, variant="binned")
     torch.cuda.synchronize()
     assert bool((out[2] == 9).all()), "nothing may be written when the batch is refused"
+
+
+@pytest.mark.parametrize("variant", ["binned", "persistent"])
+def test_noalloc_under_graph_capture(variant):
+    """The use the entry point exists for: a solve captured into a HIP graph
+    (where the context's workspace could not be grown) and replayed several
+    times, with eager work and synchronisations between the replays; every
+    replay rewrites the outputs and equals the eager solve."""
+    import torch
+
+    import paper_1902_04995_amd as rgb
+    bt = gen.concat([gen.uneven_batch(2500, m_lo=8, m_hi=3000, seed=34), gen.tiny_random_batch(500, m_max=40, seed=35)])
+    dev = rgb.DeviceBatch(bt, "cuda:0")
+    ref = _host(dev.solve(variant=variant))
+    other = rgb.DeviceBatch(gen.uniform_batch(700, 64, seed=36), "cuda:0")
+    other_ref = _host(other.solve(variant=variant))
+    out = tuple(torch.empty(bt.num_lps, dtype=dt, device="cuda") for dt in (torch.float32, torch.float32, torch.int32))
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):  # warm-up on the capture stream, outside the capture
+        rgb.solve_batch_noalloc(dev.offsets, dev.ax, dev.ay, dev.b, dev.cx, dev.cy, out=out, variant=variant,
+                                stream=side)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        rgb.solve_batch_noalloc(dev.offsets, dev.ax, dev.ay, dev.b, dev.cx, dev.cy, out=out, variant=variant,
+                                stream=torch.cuda.current_stream())
+    for rep in range(3):
+        out[0].fill_(7.0)
+        out[1].fill_(7.0)
+        out[2].fill_(9)
+        eager = other.solve(variant=variant)  # eager work of the program between replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        _same(_host(out), ref, (variant, "replay", rep))
+        _same(_host(eager), other_ref, (variant, "eager between replays", rep))
+    del g

@@ -12,7 +12,11 @@ Contents
                      (``lp3_oracle.c``), the definition written out.
   * ``brute_force3`` - the same definition in exact rational arithmetic for
                      one small LP.
-  * ``build``      - compiles both C files with gcc.
+  * ``solve_n``    - LPs in n dimensions (n = 1..6) inside a box: FP64 vertex
+                     enumeration in C (``lpn_oracle.c``), the definition
+                     written out for any n.
+  * ``brute_force_n`` - that definition in exact rational arithmetic.
+  * ``build``      - compiles the C files with gcc.
 """
 from __future__ import annotations
 
@@ -32,14 +36,17 @@ _SRC = os.path.join(_HERE, "seidel_oracle.c")
 _LIB = os.path.join(_HERE, "librgb_oracle.so")
 _SRC3 = os.path.join(_HERE, "lp3_oracle.c")
 _LIB3 = os.path.join(_HERE, "librgb_oracle3.so")
+_SRCN = os.path.join(_HERE, "lpn_oracle.c")
+_LIBN = os.path.join(_HERE, "librgb_oraclen.so")
 _lib = None
 _lib3 = None
+_libn = None
 
 
 def build(force: bool = True) -> str:
     """Compile the oracle.  -ffp-contract=off keeps every product and sum
     rounded as written (no fused multiply-add)."""
-    for src, lib in ((_SRC, _LIB), (_SRC3, _LIB3)):
+    for src, lib in ((_SRC, _LIB), (_SRC3, _LIB3), (_SRCN, _LIBN)):
         if force or not os.path.exists(lib) or os.path.getmtime(lib) < os.path.getmtime(src):
             tmp = lib + ".tmp"
             subprocess.check_call(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
@@ -309,3 +316,160 @@ def brute_force3(ax, ay, az, b, c, M):
 
 def brute_force3_batch(batch):
     return [brute_force3(*batch.lp(k)[:4], batch.lp(k)[4], batch.box) for k in range(batch.num_lps)]
+
+
+# ---------------------------------------------------------------------------
+
+def _loadn():
+    global _libn
+    if _libn is None:
+        if not os.path.exists(_LIBN) or os.path.getmtime(_LIBN) < os.path.getmtime(_SRCN):
+            build(force=False)
+        lib = ctypes.CDLL(_LIBN)
+        f = lib.rgb_oraclen_solve_range
+        P = ctypes.c_void_p
+        f.argtypes = [ctypes.c_int] + [ctypes.c_int64] * 4 + [P] * 4 + [ctypes.c_double] + [P] * 3
+        f.restype = ctypes.c_int
+        _libn = lib
+    return _libn
+
+
+def solve_n(batch, threads: int | None = None, lp_begin: int = 0, lp_end: int | None = None):
+    """Solve LPs [lp_begin, lp_end) of a ``genn.BatchN`` (n = batch.dim).
+    Returns a dict with x (B, n) float64, status (int32) and def (B, n) int32
+    (the hyperplanes of the optimal vertex: rows 0..m-1, box faces -1..-2n),
+    plus the thread count.  LPs are split over threads by equal sum of
+    (m + 2n)^n (the enumeration's cost)."""
+    lib = _loadn()
+    n = int(batch.a.shape[0])
+    offsets = np.ascontiguousarray(batch.offsets, dtype=np.int64)
+    a = np.ascontiguousarray(batch.a, dtype=np.float32)
+    b = np.ascontiguousarray(batch.b, dtype=np.float32)
+    c = np.ascontiguousarray(batch.c, dtype=np.float32)
+    B = offsets.shape[0] - 1
+    if lp_end is None:
+        lp_end = B
+    out = {"x": np.full((B, n), np.nan), "status": np.full(B, INVALID, dtype=np.int32),
+           "def": np.full((B, n), -100, dtype=np.int32)}
+    if threads is None:
+        threads = max(1, len(os.sched_getaffinity(0)))
+    cnt = lp_end - lp_begin
+    if cnt <= 0:
+        out["threads"] = 0
+        return out
+    threads = max(1, min(threads, cnt))
+    m = np.diff(offsets[lp_begin:lp_end + 1]).astype(np.float64) + 2.0 * n
+    work = np.concatenate([[0.0], np.cumsum(m ** n)])
+    cuts = np.searchsorted(work, np.linspace(0, work[-1], threads + 1)[1:-1]) + lp_begin
+    bounds = [lp_begin] + sorted(set(int(t) for t in cuts if lp_begin < t < lp_end)) + [lp_end]
+    N = int(b.shape[0])
+    args = [_ptr(offsets), _ptr(a), _ptr(b), _ptr(c), ctypes.c_double(float(batch.box)),
+            _ptr(out["x"]), _ptr(out["status"]), _ptr(out["def"])]
+    rc = []
+
+    def run(s, e):
+        if e > s:
+            rc.append(lib.rgb_oraclen_solve_range(n, s, e, B, N, *args))
+
+    ths = [threading.Thread(target=run, args=(bounds[i], bounds[i + 1])) for i in range(len(bounds) - 1)]
+    for t in ths:
+        t.start()
+    for t in ths:
+        t.join()
+    if any(r != 0 for r in rc):
+        raise ValueError(f"dimension {n} is outside 1..6")
+    out["threads"] = len(ths)
+    return out
+
+
+def _int_row(vals):
+    """Fractions scaled by a positive integer into integers (a row's
+    constraint, or the objective's argmax, does not change)."""
+    from math import lcm
+    den = 1
+    for v in vals:
+        den = lcm(den, v.denominator)
+    return [int(v * den) for v in vals]
+
+
+def _solve_int(A, r):
+    """Solve the integer system A v = r exactly by fraction-free Gauss-Jordan
+    elimination (every division is exact).  Returns (N, D) with v = N / D and
+    D > 0, or None when the system is singular."""
+    n = len(A)
+    M = [list(A[i]) + [r[i]] for i in range(n)]
+    prev = 1
+    for k in range(n):
+        p = next((i for i in range(k, n) if M[i][k] != 0), None)
+        if p is None:
+            return None
+        M[k], M[p] = M[p], M[k]
+        pk = M[k][k]
+        for i in range(n):
+            if i == k:
+                continue
+            mik = M[i][k]
+            M[i] = [(pk * M[i][j] - mik * M[k][j]) // prev if j != k else 0 for j in range(n + 1)]
+        prev = pk
+    D = M[0][0]
+    N = [M[i][n] for i in range(n)]
+    if D < 0:
+        D, N = -D, [-t for t in N]
+    return N, D
+
+
+def brute_force_n(a, b, c, M):
+    """Exact rational vertex enumeration of one LP in n dimensions inside the
+    box |x_k| <= M: a is (n, m), b (m,), c (n,).  Every row is scaled to
+    integers and each vertex is solved in exact integer arithmetic.  Returns
+    (status, x as a tuple of Fractions or None)."""
+    from itertools import combinations
+    a = np.asarray(a)
+    n, m = a.shape
+    vals = list(a.ravel()) + list(b) + list(c)
+    if not all(np.isfinite(v) for v in vals) or not (np.isfinite(M) and M > 0):
+        return INVALID, None
+    Mf = _frac(M)
+    rows = []
+    for i in range(m):
+        ai = [_frac(a[k, i]) for k in range(n)]
+        if all(t == 0 for t in ai):
+            if _frac(b[i]) < 0:
+                return INFEASIBLE, None
+            continue
+        r = _int_row(ai + [_frac(b[i])])
+        rows.append((r[:n], r[n]))
+    for k in range(n):
+        for sgn in (1, -1):
+            e = [0] * n
+            e[k] = sgn * Mf.denominator
+            rows.append((e, Mf.numerator))
+    cf = _int_row([_frac(v) for v in c])
+    best = None  # (c.N, N, D)
+    for sub in combinations(range(len(rows)), n):
+        sol = _solve_int([rows[i][0] for i in sub], [rows[i][1] for i in sub])
+        if sol is None:
+            continue
+        N, D = sol
+        f = sum(ci * t for ci, t in zip(cf, N))
+        if best is not None:
+            bf, bN, bD = best
+            lhs, rhs = f * bD, bf * D
+            if lhs < rhs:
+                continue
+            if lhs == rhs:
+                # equal objective: the smaller x_1, then x_2, ... wins
+                cmp = next(((t * bD > u * D) - (t * bD < u * D) for t, u in zip(N, bN) if t * bD != u * D), 0)
+                if cmp >= 0:
+                    continue
+        if all(sum(ai * t for ai, t in zip(r, N)) <= bb * D for r, bb in rows):
+            best = (f, N, D)
+    if best is None:
+        return INFEASIBLE, None
+    _, N, D = best
+    v = tuple(Fraction(t, D) for t in N)
+    return (UNBOUNDED if max(abs(t) for t in v) == Mf else OPTIMAL), v
+
+
+def brute_force_n_batch(batch):
+    return [brute_force_n(*batch.lp(k), batch.box) for k in range(batch.num_lps)]

@@ -104,14 +104,14 @@ def _unit_vectors(rng, n):
 def _insert(rng, n_rand, rand_rows, specials, n_spec):
     """Rows of B LPs: LP k gets its n_rand[k] random rows (LP-major, in order)
     with the first n_spec[k] rows of specials[k] inserted at uniform positions.
-    Returns offsets and an (N, 4) float64 array."""
+    Returns offsets and an (N, W) float64 array, W the width of a row."""
     B = n_rand.shape[0]
     K = specials.shape[1]
     sizes = n_rand + n_spec
     offsets = np.zeros(B + 1, dtype=np.int64)
     np.cumsum(sizes, out=offsets[1:])
     N = int(offsets[-1])
-    rows = np.empty((N, 4))
+    rows = np.empty((N, rand_rows.shape[1]))
     pos = np.zeros((B, K), dtype=np.int64)
     for j in range(K):
         active = j < n_spec

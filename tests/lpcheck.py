@@ -214,3 +214,45 @@ def kkt_residual3(A, b, c, x, tight_tol=1e-7):
         return viol, float(np.linalg.norm(c))
     lam, res = nnls(A[tight].T, c)
     return viol, float(res / max(1e-300, np.linalg.norm(c)))
+
+
+def parse_golden_n(path):
+    """n-dimensional fixtures: lp NAME / dim n / c c_1 .. c_n / box M /
+    row a_1 .. a_n b ... / expect optimal|unbounded x_1 .. x_n  or
+    expect infeasible / end."""
+    lps, cur = [], None
+    with open(path) as f:
+        for raw in f:
+            line = raw.split("#", 1)[0].strip()
+            if not line:
+                continue
+            tok = line.split()
+            if tok[0] == "lp":
+                cur = {"name": tok[1], "rows": [], "c": None, "box": None, "expect": None, "dim": None}
+            elif tok[0] == "dim":
+                cur["dim"] = int(tok[1])
+            elif tok[0] == "c":
+                cur["c"] = tuple(float(t) for t in tok[1:])
+            elif tok[0] == "box":
+                cur["box"] = float(tok[1])
+            elif tok[0] == "row":
+                cur["rows"].append(tuple(float(t) for t in tok[1:]))
+            elif tok[0] == "expect":
+                st = {"optimal": OPTIMAL, "infeasible": INFEASIBLE, "unbounded": UNBOUNDED}[tok[1]]
+                x = tuple(float(t) for t in tok[2:]) if st != INFEASIBLE else None
+                cur["expect"] = (st, x)
+            elif tok[0] == "end":
+                n = cur["dim"]
+                assert len(cur["c"]) == n and all(len(r) == n + 1 for r in cur["rows"]), cur["name"]
+                assert cur["expect"][1] is None or len(cur["expect"][1]) == n, cur["name"]
+                lps.append(cur)
+                cur = None
+    return lps
+
+
+def golden_n_batch(lp):
+    """A one-LP BatchN holding one fixture."""
+    from paper_1902_04995_amd import genn
+    n = lp["dim"]
+    rows = np.array(lp["rows"], dtype=np.float64).reshape(-1, n + 1)
+    return genn.from_rows([rows], [lp["c"]], lp["box"], name=lp["name"])

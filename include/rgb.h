@@ -437,6 +437,45 @@ rgb_err_t rgb_solve3_batch(rgb_ctx_t* ctx, int64_t num_lps, int64_t num_constrai
                            const float* cy, const float* cz, double box, float* x_out, float* y_out, float* z_out,
                            int32_t* status_out, int32_t lanes_per_lp, void* stream, void* ev_begin, void* ev_end);
 
+/* ---------------------------------------------------------------------------
+ * Batched LPs in n = 2..5 dimensions (the method of Sec. 2.1 in n
+ * dimensions, recursive in the dimension; the paper names higher dimensions
+ * as its next step in Sec. 6).
+ *
+ * LP k: maximize c_k.x over x in R^n subject to a_i.x <= b_i for its rows
+ * offsets[k] <= i < offsets[k+1], and the bounding rows |x_j| <= box of
+ * Sec. 2.1 (one box for the batch; the rows are not stored).  The result is
+ * the lexicographically smallest maximiser: among the points maximising c.x
+ * the one with the smallest x_1, then x_2, and so on.  Rows are taken in the
+ * order given (the caller's random order gives Seidel's expected bound).
+ *
+ * Layout (coordinate-major SoA): offsets int64 [num_lps + 1]; a float
+ * [dim * num_constraints] with component j of row i at a[j * num_constraints
+ * + i]; b float [num_constraints]; c float [dim * num_lps] with component j
+ * of LP k's objective at c[j * num_lps + k]; outputs x float [dim * num_lps]
+ * (same layout as c) and status int32 [num_lps].  All pointers are DEVICE
+ * memory owned by the caller.  Status: OPTIMAL; INFEASIBLE (x NaN);
+ * UNBOUNDED when the optimum lies on a face of the box (max_j |x_j| >= box
+ * (1 - 1e-9): the LP without the box is unbounded, or its optimum lies
+ * outside the box), with x the optimum inside the box; INVALID (x NaN) for
+ * non-finite rows or objective and offsets that are out of range, decreasing
+ * or span more than 2^30 rows.  Arithmetic is FP64 on the FP32 inputs, with
+ * relative tolerances of 1e-11 on row violations and 1e-12 on parallel rows
+ * and ties.
+ *
+ * lanes_per_lp: 0 (= 16) or 4, 8, 16, 32, 64 lanes per LP.  ev_begin,
+ * ev_end: optional hipEvent_t recorded on `stream` around the kernel.
+ * Enqueued on `stream` (0 = null stream) on ctx's device; returns before the
+ * solve completes.  Errors (synchronous, nothing enqueued): INVALID_ARG for
+ * a null context or pointer, negative sizes, dim outside 2..5, box not
+ * finite and positive or an unsupported lanes_per_lp; TOO_LARGE above
+ * 2^31 - 1 LPs; DEVICE when the launch fails.
+ * ------------------------------------------------------------------------- */
+rgb_err_t rgb_solven_batch(rgb_ctx_t* ctx, int32_t dim, int64_t num_lps, int64_t num_constraints,
+                           const int64_t* offsets, const float* a, const float* b, const float* c, double box,
+                           float* x_out, int32_t* status_out, int32_t lanes_per_lp, void* stream, void* ev_begin,
+                           void* ev_end);
+
 #ifdef __cplusplus
 }
 #endif

@@ -158,6 +158,8 @@ def lib():
         L.rgb_reduce_bench_run.restype = I32
         L.rgb_solve3_batch.argtypes = [P, I64, I64] + [P] * 8 + [ctypes.c_double] + [P] * 4 + [I32, P, P, P]
         L.rgb_solve3_batch.restype = I32
+        L.rgb_solven_batch.argtypes = [P, I32, I64, I64] + [P] * 4 + [ctypes.c_double] + [P] * 2 + [I32, P, P, P]
+        L.rgb_solven_batch.restype = I32
         _lib = L
     return _lib
 
@@ -707,3 +709,68 @@ class DeviceBatch3:
 
     def solve(self, **kw):
         return solve3_batch(self.offsets, self.ax, self.ay, self.az, self.b, self.cx, self.cy, self.cz, self.box, **kw)
+
+
+# ---------------------------------------------------------------------------
+# LPs in n = 2..5 dimensions (rgb_solven_batch)
+
+def solven_batch(offsets, a, b, c, box, *, lanes_per_lp=0, out=None, stream=None, ctx: Context | None = None,
+                 events=None):
+    """Solve a batch of n-dimensional LPs held in CUDA tensors (offsets
+    int64[B+1]; a float32[n, N] with row i's normal in column i; b
+    float32[N]; c float32[n, B]) inside the box |x_k| <= box.  Enqueues on
+    ``stream`` (default: torch's current stream) and returns (x, status):
+    x float32[n, B], status int32[B], valid once that stream has run the work.
+    ``events`` = (begin, end) torch.cuda.Events recorded around the kernel."""
+    import torch
+    dev = offsets.device
+    if dev.type != "cuda":
+        raise ValueError("solven_batch needs CUDA tensors")
+    _check_tensor(offsets, "offsets", torch.int64, dev)
+    for name, t in (("a", a), ("b", b), ("c", c)):
+        _check_tensor(t, name, torch.float32, dev)
+    if a.dim() != 2 or c.dim() != 2 or a.shape[0] != c.shape[0]:
+        raise ValueError("a and c must be (n, N) and (n, B)")
+    n = int(a.shape[0])
+    B = offsets.numel() - 1
+    N = int(a.shape[1])
+    if B < 0 or b.numel() != N or c.shape[1] != B:
+        raise ValueError("inconsistent batch shapes")
+    if out is None:
+        out = (torch.empty((n, B), dtype=torch.float32, device=dev), torch.empty(B, dtype=torch.int32, device=dev))
+    else:
+        if len(out) != 2:
+            raise ValueError("out must be (x, status)")
+        _check_tensor(out[0], "out x", torch.float32, dev)
+        _check_tensor(out[1], "out status", torch.int32, dev)
+        if tuple(out[0].shape) != (n, B) or out[1].numel() != B:
+            raise ValueError(f"out must hold x ({n}, {B}) and status ({B},)")
+    x, st = out
+    ctx = ctx or context(dev.index or 0)
+    if stream is None:
+        stream = torch.cuda.current_stream(dev)
+    ev = (None, None) if events is None else tuple(_event_handle(e) for e in events)
+    rc = lib().rgb_solven_batch(ctx.handle, n, B, N, _ptr(offsets), _ptr(a), _ptr(b), _ptr(c),
+                                ctypes.c_double(float(box)), _ptr(x), _ptr(st), int(lanes_per_lp),
+                                ctypes.c_void_p(stream.cuda_stream), ctypes.c_void_p(ev[0]), ctypes.c_void_p(ev[1]))
+    if rc != 0:
+        raise RgbError(f"rgb_solven_batch failed ({rc})")
+    return out
+
+
+class DeviceBatchN:
+    """A genn.BatchN copied to device memory."""
+
+    def __init__(self, batch, device="cuda"):
+        import numpy as np
+        import torch
+        t = lambda v: torch.from_numpy(np.ascontiguousarray(v)).to(device)
+        self.offsets = t(batch.offsets)
+        self.a, self.b, self.c = t(batch.a), t(batch.b), t(batch.c)
+        self.box = float(batch.box)
+        self.dim = batch.dim
+        self.num_lps = batch.num_lps
+        self.num_constraints = batch.num_constraints
+
+    def solve(self, **kw):
+        return solven_batch(self.offsets, self.a, self.b, self.c, self.box, **kw)

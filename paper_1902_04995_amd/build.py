@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librgb.so")
 BUILD_DIR = os.path.join(os.path.dirname(HERE), "_build")
 SOURCES = ["rgb_kernels.hip", "rgb_api.hip", "rgb_server.hip", "rgb_host.hip", "rgb_crowd.hip", "rgb_reduce.hip",
-           "rgb_seidel3.hip", "rgb_table.cpp"]
+           "rgb_seidel3.hip", "rgb_seidelN.hip", "rgb_table.cpp"]
 ARCH = os.environ.get("RGB_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -1,0 +1,252 @@
+"""GPU parity of the n-dimensional solver (rgb_solven_batch, n = 2..5) against
+the n-dimensional oracle.
+
+Bar (per LP): status bit-exact; for OPTIMAL and UNBOUNDED (the optimum on the
+box) ||x - x_oracle||_inf <= 1e-4 * max(1, |x_oracle|) per component (an FP64
+solve rounded to FP32 against FP64 vertex enumeration).  Every lane width must
+give bit-identical results (the bound reductions are exact minima and every
+lane of a group solves the same small systems).
+"""
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import lpcheck
+from lpcheck import INFEASIBLE, INVALID, OPTIMAL, UNBOUNDED
+from paper_1902_04995_amd import genn
+
+pytestmark = pytest.mark.gpu
+X_RTOL = 1e-4
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def rgb():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_1902_04995_amd as rgb
+    rgb.lib()
+    return rgb
+
+
+def _run(rgb, bt, g=0):
+    import torch
+    dev = rgb.DeviceBatchN(bt, "cuda:0")
+    x, st = dev.solve(lanes_per_lp=g)
+    torch.cuda.synchronize()
+    return st.cpu().numpy(), np.ascontiguousarray(x.cpu().numpy().T)
+
+
+def _mismatches(ref, st, x, idx=None):
+    rs, rx = ref["status"], ref["x"]
+    if idx is not None:
+        rs, rx = rs[idx], rx[idx]
+    bad_s = np.flatnonzero(st != rs)
+    has_x = (rs == OPTIMAL) | (rs == UNBOUNDED)
+    err = np.abs(x.astype(np.float64) - rx) > X_RTOL * np.maximum(1.0, np.abs(rx))
+    bad_x = np.flatnonzero(has_x & (st == rs) & err.any(axis=1))
+    return bad_s, bad_x
+
+
+def _check(bt, ref, st, x, label):
+    bs, bx = _mismatches(ref, st, x)
+    msg = f"{label}: {len(bs)} status / {len(bx)} x mismatches of {bt.num_lps}"
+    for k in list(bs[:5]) + list(bx[:5]):
+        msg += f"\n  lp {k} m={bt.sizes()[k]} got st={st[k]} x={x[k]} ref st={ref['status'][k]} x={ref['x'][k]}"
+    assert len(bs) + len(bx) == 0, msg
+
+
+def _batches(n):
+    return {
+        "int_k1": lambda: genn.tiny_integer_n_batch(n, 2000, m_max=3 * n, K=1, seed=60 + n),
+        "int_k2": lambda: genn.tiny_integer_n_batch(n, 2000, m_max=2 * n + 2, K=2, seed=61 + n),
+        "int_k2_more": lambda: genn.concat_n([genn.tiny_integer_n_batch(n, 3000, m_max=2 * n + 2, K=2, seed=s)
+                                              for s in (100, 101, 102)]),
+        "int_k3": lambda: genn.tiny_integer_n_batch(n, 3000, m_max=2 * n + 2, K=3, seed=76 + n),
+        "int_k1_boxed": lambda: genn.tiny_integer_n_batch(n, 1000, m_max=n + 2, K=1, seed=62 + n, boxed=True),
+        "int_k2_boxed": lambda: genn.tiny_integer_n_batch(n, 1000, m_max=n + 2, K=2, seed=63 + n, boxed=True),
+        "random": lambda: genn.tiny_random_n_batch(n, 2000, m_max=4 * n + 4, seed=64 + n),
+        "uniform_small": lambda: genn.uniform_n_batch(n, 800, 6 * n, seed=65 + n, infeasible_frac=0.1,
+                                                      unbounded_frac=0.1),
+    }
+
+
+CASES = [(n, name) for n in (2, 3, 4, 5) for name in _batches(n)]
+
+
+@pytest.mark.parametrize("n,name", CASES, ids=[f"{n}d_{name}" for n, name in CASES])
+def test_seidelN_matches_oracle(rgb, oracle_lib, n, name):
+    bt = _batches(n)[name]()
+    ref = oracle_lib.solve_n(bt)
+    _say(f"[seidelN] {n}d {name}: {bt.num_lps} LPs, {bt.num_constraints} rows, status mix "
+         f"{np.bincount(ref['status'], minlength=4).tolist()}")
+    st, x = _run(rgb, bt)
+    _check(bt, ref, st, x, f"{n}d {name}")
+
+
+@pytest.mark.parametrize("n", [3, 4, 5])
+def test_seidelN_lane_widths_bit_identical(rgb, oracle_lib, n):
+    bt = genn.concat_n([genn.uniform_n_batch(n, 300, 12 * n, seed=66 + n),
+                        genn.tiny_integer_n_batch(n, 300, m_max=2 * n, K=2, seed=67 + n, box=1.0e4),
+                        genn.uniform_n_batch(n, 100, n + 1, seed=68 + n)])
+    st0, x0 = _run(rgb, bt, 16)
+    _say(f"[seidelN] {n}d widths: {bt.num_lps} LPs")
+    for g in (4, 8, 32, 64):
+        st, x = _run(rgb, bt, g)
+        assert np.array_equal(st, st0), g
+        assert np.array_equal(x.view(np.int32), x0.view(np.int32)), g
+    _check(bt, oracle_lib.solve_n(bt), st0, x0, f"{n}d width mix")
+
+
+def test_seidelN_hand_solved_golden(rgb):
+    lps = lpcheck.parse_golden_n(os.path.join(lpcheck.GOLDEN, "lpn_hand.txt"))
+    for lp in lps:
+        for g in (4, 16, 64):
+            st, x = _run(rgb, lpcheck.golden_n_batch(lp), g)
+            want, xv = lp["expect"]
+            assert st[0] == want, (lp["name"], g, st[0])
+            if xv is None:
+                assert np.isnan(x[0]).all(), lp["name"]
+            else:
+                np.testing.assert_allclose(x[0], xv, rtol=1e-6, atol=1e-6, err_msg=lp["name"])
+
+
+def test_seidelN_edges(rgb, oracle_lib):
+    import torch
+    # empty batch: nothing enqueued, no error
+    z64 = torch.zeros(1, dtype=torch.int64, device="cuda")
+    a0 = torch.empty((4, 0), dtype=torch.float32, device="cuda")
+    e = torch.empty(0, dtype=torch.float32, device="cuda")
+    out = rgb.solven_batch(z64, a0, e, torch.empty((4, 0), dtype=torch.float32, device="cuda"), 10.0)
+    assert out[1].numel() == 0
+    for n in (2, 4, 5):
+        # empty LPs, NaN / inf rows, an infinite objective
+        bt = genn.tiny_random_n_batch(n, 40, m_max=12, m_min=0, seed=69 + n)
+        sizes = bt.sizes()
+        a = bt.a.copy()
+        b = bt.b.copy()
+        c = bt.c.copy()
+        big = np.flatnonzero(sizes >= 3)
+        k1, k2, k3 = (int(t) for t in big[:3])
+        a[n - 1, bt.offsets[k1] + 2] = np.nan
+        b[bt.offsets[k2] + sizes[k2] - 1] = -np.inf
+        a[0, bt.offsets[k3]] = np.inf
+        c[n - 1, 5] = np.inf
+        bad = bt.with_rows(a=a, b=b, c=c)
+        ref = oracle_lib.solve_n(bad)
+        st, x = _run(rgb, bad)
+        assert st[k1] == INVALID and st[k2] == INVALID and st[k3] == INVALID and st[5] == INVALID, n
+        _check(bad, ref, st, x, f"{n}d edges")
+        assert (sizes == 0).any() and (st[sizes == 0] == UNBOUNDED).all()
+        # offsets out of range, decreasing: INVALID, and nothing read out of range
+        dev = rgb.DeviceBatchN(bt, "cuda:0")
+        offs = dev.offsets.clone()
+        offs[3] = bt.num_constraints + 100
+        offs[7] = -5
+        x_, s_ = rgb.solven_batch(offs, dev.a, dev.b, dev.c, bt.box)
+        torch.cuda.synchronize()
+        s_ = s_.cpu().numpy()
+        assert s_[2] == INVALID and s_[3] == INVALID and s_[6] == INVALID and s_[7] == INVALID
+        # argument errors are synchronous and enqueue nothing
+        for box in (0.0, -1.0, float("inf"), float("nan")):
+            with pytest.raises(rgb.RgbError):
+                rgb.solven_batch(dev.offsets, dev.a, dev.b, dev.c, box)
+        with pytest.raises(rgb.RgbError):
+            dev.solve(lanes_per_lp=12)
+    # a dimension outside 2..5 is refused by the library
+    bt = genn.tiny_random_n_batch(6, 4, m_max=5, seed=75)
+    dev = rgb.DeviceBatchN(bt, "cuda:0")
+    with pytest.raises(rgb.RgbError):
+        dev.solve()
+
+
+@pytest.mark.parametrize("name", ["uniform4", "uniform5"])
+def test_seidelN_full_size_sampled(rgb, oracle_lib, name):
+    """The measurement workloads (65,536 LPs of 128 and 64 hyperplanes) in one
+    launch at the default width; sampled LPs against the oracle (the LPs
+    planted infeasible or open among them), and the status mix the generator
+    plants (5% infeasible, 2% on the box)."""
+    import torch
+    bt = genn.make_config_n(name, seed=0)
+    st, x = _run(rgb, bt)
+    rng = np.random.default_rng(70)
+    idx = np.sort(np.concatenate([rng.choice(bt.num_lps, 24, replace=False),
+                                  rng.choice(np.flatnonzero(bt.kind == 1), 4, replace=False),
+                                  rng.choice(np.flatnonzero(bt.kind == 2), 4, replace=False)]))
+    idx = np.unique(idx)
+    ref = oracle_lib.solve_n(bt.subset(idx))
+    bs, bx = _mismatches(ref, st[idx], x[idx])
+    assert len(bs) + len(bx) == 0, (bs[:5], bx[:5])
+    counts = np.bincount(st, minlength=4)
+    _say(f"[seidelN] {name} full size status mix {counts.tolist()}")
+    assert counts[INFEASIBLE] == int(round(0.05 * bt.num_lps))
+    assert counts[UNBOUNDED] == int(round(0.02 * bt.num_lps))
+    assert counts[INVALID] == 0
+    st2, x2 = _run(rgb, bt)
+    assert np.array_equal(st2, st) and np.array_equal(x2.view(np.int32), x.view(np.int32))
+    torch.cuda.empty_cache()
+
+
+def test_seidelN_one_large_lp(rgb):
+    """One 4D LP of 100,000 hyperplanes tangent to the unit sphere (random
+    directions and order) among small ones: checked by properties that hold
+    at any size -- every row satisfied, a KKT certificate on the tight rows,
+    and c.x >= |c| (the polytope contains the unit ball)."""
+    n, m = 4, 100_000
+    rng = np.random.default_rng(71)
+    nrm = rng.standard_normal((m, n))
+    nrm /= np.linalg.norm(nrm, axis=1, keepdims=True)
+    nrm = nrm.astype(np.float32)
+    c = np.array([0.3, -0.5, 0.8, 0.1], np.float32)
+    big = genn.BatchN(np.array([0, m], np.int64), np.ascontiguousarray(nrm.T), np.ones(m, np.float32),
+                      c[:, None].copy(), np.zeros(1, np.int8), 1e4)
+    bt = genn.concat_n([genn.uniform_n_batch(n, 2000, 20, seed=72), big, genn.uniform_n_batch(n, 1000, 9, seed=73)])
+    k = 2000
+    for g in (16, 64):
+        st, x = _run(rgb, bt, g)
+        assert st[k] == OPTIMAL, (g, st[k])
+        xk = x[k].astype(np.float64)
+        viol, resid = lpcheck.kkt_residual3(nrm.astype(np.float64), np.ones(m), c.astype(np.float64), xk,
+                                            tight_tol=2e-6)
+        assert viol <= 2e-6 and resid <= 1e-3, (g, viol, resid)
+        cn = float(np.linalg.norm(c.astype(np.float64)))
+        assert float(c.astype(np.float64) @ xk) >= cn * (1 - 1e-6)
+
+
+def test_seidelN_lp_over_row_limit(rgb, oracle_lib):
+    """One 4D LP of 2^30 + 1 rows (over the per-LP limit, ~21 GB of real rows
+    in device memory) is INVALID and never read; the 100-row LP after it is
+    still solved, at two lane widths."""
+    import torch
+    n = 4
+    big = (1 << 30) + 1
+    N = big + 100
+    free, _ = torch.cuda.mem_get_info()
+    if free < 4 * (n + 1) * N + (2 << 30):
+        pytest.skip(f"needs {4 * (n + 1) * N / 2**30:.1f} GiB of free device memory, {free / 2**30:.1f} free")
+    small = genn.uniform_n_batch(n, 1, 100, seed=74, infeasible_frac=0.0, unbounded_frac=0.0)
+    _say(f"[seidelN] case=over_limit rows={N}")
+    a = torch.zeros((n, N), dtype=torch.float32, device="cuda")
+    a[:, big:] = torch.from_numpy(small.a).cuda()
+    b = torch.zeros(N, dtype=torch.float32, device="cuda")
+    b[big:] = torch.from_numpy(small.b).cuda()
+    offs = torch.tensor([0, big, N], dtype=torch.int64, device="cuda")
+    c = torch.from_numpy(np.concatenate([np.full((n, 1), 0.3, np.float32), small.c], axis=1)).cuda()
+    ref = oracle_lib.solve_n(small)
+    for g in (16, 64):
+        x, st = rgb.solven_batch(offs, a, b, c, small.box, lanes_per_lp=g)
+        torch.cuda.synchronize()
+        st = st.cpu().numpy()
+        xv = np.ascontiguousarray(x.cpu().numpy().T)
+        assert st[0] == INVALID and np.isnan(xv[0]).all(), g
+        bs, bx = _mismatches(ref, st[1:], xv[1:])
+        assert len(bs) + len(bx) == 0, (g, st[1], xv[1], ref["status"], ref["x"])
+    del a, b
+    torch.cuda.empty_cache()

@@ -418,6 +418,7 @@ def main():
     ap.add_argument("--no-host", action="store_true", help="skip the host-to-host (transfer-inclusive) leg")
     ap.add_argument("--no-crowd", action="store_true", help="skip the crowd time-step leg")
     ap.add_argument("--no-seidel3", action="store_true", help="skip the 3D solver leg")
+    ap.add_argument("--no-seidelN", action="store_true", help="skip the 4D and 5D solver legs")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -452,6 +453,14 @@ def main():
         from paper_1902_04995_amd import gen3, seidel3_run
         seidel3 = seidel3_run.measure(rgb, gen3.make_config3("uniform3", seed=0), steps=10)
         print(f"[bench] 3D: {json.dumps(seidel3)}", file=sys.stderr, flush=True)
+
+    seidelN = None
+    if not args.no_seidelN:
+        from paper_1902_04995_amd import genn, seidelN_run
+        seidelN = {}
+        for wl in ("uniform4", "uniform5"):
+            seidelN[wl] = seidelN_run.measure(rgb, genn.make_config_n(wl, seed=0), lanes=(4, 8, 16), steps=10)
+            print(f"[bench] {wl}: {json.dumps(seidelN[wl])}", file=sys.stderr, flush=True)
 
     served = None
     if args.served_requests > 0:
@@ -491,6 +500,7 @@ def main():
         "host_path": host,
         "crowd_loop": crowd,
         "seidel3": seidel3,
+        "seidelN": seidelN,
         "served": served,
     }
     print(json.dumps(line))

@@ -463,8 +463,9 @@ rgb_err_t rgb_solve3_batch(rgb_ctx_t* ctx, int64_t num_lps, int64_t num_constrai
  * relative tolerances of 1e-11 on row violations and 1e-12 on parallel rows
  * and ties.
  *
- * lanes_per_lp: 0 (= 16) or 4, 8, 16, 32, 64 lanes per LP.  ev_begin,
- * ev_end: optional hipEvent_t recorded on `stream` around the kernel.
+ * lanes_per_lp: 0 (= 16, or 8 for dim 5: the measured best) or 4, 8, 16,
+ * 32, 64 lanes per LP.  ev_begin, ev_end: optional hipEvent_t recorded on
+ * `stream` around the kernel.
  * Enqueued on `stream` (0 = null stream) on ctx's device; returns before the
  * solve completes.  Errors (synchronous, nothing enqueued): INVALID_ARG for
  * a null context or pointer, negative sizes, dim outside 2..5, box not

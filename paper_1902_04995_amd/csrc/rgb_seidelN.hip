@@ -12,6 +12,8 @@
 //                that started it: its start is the best point of S inside the
 //                box faces the objective points at, then a scan of the rows
 //                against it, each violated row starting level K - 1;
+//   level 2      the same on a plane, written once as x = q + u e + v f, so
+//                that each violated row gives its line with a few products;
 //   level 1      S is a line p + t d: every earlier row is one work unit
 //                (Sec. 3) giving a bound on t, split over the group's lanes
 //                and reduced to the bound the objective climbs towards.
@@ -43,7 +45,7 @@
 // 256-lane block.  The scans test G rows at a time and find the first violated
 // one with a ballot; the work units of a line are split over the G lanes and
 // reduced with cross-lane moves.  The small linear systems (a subspace's start
-// vertices by Cramer's rule, the line by elimination with pivoting) are solved
+// vertices by Cramer's rule, a plane by elimination with pivoting) are solved
 // redundantly by every lane of the group.
 #include <hip/hip_runtime.h>
 
@@ -114,16 +116,18 @@ __device__ __forceinline__ bool solve_small(const double (&A)[R][R], const doubl
     } else if constexpr (R == 2) {
         const double det = A[0][0] * A[1][1] - A[0][1] * A[1][0];
         if (!(__builtin_fabs(det) > kTolSing * norms)) return false;
-        v[0] = (r[0] * A[1][1] - A[0][1] * r[1]) / det;
-        v[1] = (A[0][0] * r[1] - r[0] * A[1][0]) / det;
+        const double inv = 1.0 / det;
+        v[0] = (r[0] * A[1][1] - A[0][1] * r[1]) * inv;
+        v[1] = (A[0][0] * r[1] - r[0] * A[1][0]) * inv;
     } else {
         auto det3 = [](double a0, double a1, double a2, double b0, double b1, double b2, double c0, double c1,
                        double c2) { return a0 * (b1 * c2 - b2 * c1) - a1 * (b0 * c2 - b2 * c0) + a2 * (b0 * c1 - b1 * c0); };
         const double det = det3(A[0][0], A[0][1], A[0][2], A[1][0], A[1][1], A[1][2], A[2][0], A[2][1], A[2][2]);
         if (!(__builtin_fabs(det) > kTolSing * norms)) return false;
-        v[0] = det3(r[0], A[0][1], A[0][2], r[1], A[1][1], A[1][2], r[2], A[2][1], A[2][2]) / det;
-        v[1] = det3(A[0][0], r[0], A[0][2], A[1][0], r[1], A[1][2], A[2][0], r[2], A[2][2]) / det;
-        v[2] = det3(A[0][0], A[0][1], r[0], A[1][0], A[1][1], r[1], A[2][0], A[2][1], r[2]) / det;
+        const double inv = 1.0 / det;
+        v[0] = det3(r[0], A[0][1], A[0][2], r[1], A[1][1], A[1][2], r[2], A[2][1], A[2][2]) * inv;
+        v[1] = det3(A[0][0], r[0], A[0][2], A[1][0], r[1], A[1][2], A[2][0], r[2], A[2][2]) * inv;
+        v[2] = det3(A[0][0], A[0][1], r[0], A[1][0], A[1][1], r[1], A[2][0], A[2][1], r[2]) * inv;
     }
     return true;
 }
@@ -138,6 +142,7 @@ struct Group {
     int gl, gbase;
     uint64_t gmask;
     double c[D];
+    double cn;    // |c|_1
     double x[D];  // the current vertex
     int H[D];     // rows whose hyperplanes define the current subspace
     int status;   // kAlive while the LP is being solved
@@ -172,17 +177,12 @@ struct Group {
         return lhs - r.b > kTolViol * mag;
     }
 
-    // Does v beat w under the perturbed objective (c.v larger, then x_1,
-    // x_2, ... smaller)?
-    __device__ __forceinline__ bool better(const double (&v)[D], const double (&w)[D]) const {
-        double fv = 0.0, fw = 0.0, vn = 0.0, cn = 0.0;
+    // Does v (objective value fv) beat w (fw) under the perturbed objective:
+    // c.v larger, then x_1, x_2, ... smaller?
+    __device__ __forceinline__ bool better(const double (&v)[D], double fv, const double (&w)[D], double fw) const {
+        double vn = 0.0;
 #pragma unroll
-        for (int k = 0; k < D; ++k) {
-            fv += c[k] * v[k];
-            fw += c[k] * w[k];
-            vn += __builtin_fabs(v[k]);
-            cn += __builtin_fabs(c[k]);
-        }
+        for (int k = 0; k < D; ++k) vn += __builtin_fabs(v[k]);
         const double tol = kTolTie * (cn * vn + vn + 1.0);
         if (fv > fw + tol) return true;
         if (fv < fw - tol) return false;
@@ -193,18 +193,21 @@ struct Group {
         }
         return false;
     }
+    __device__ __forceinline__ double objective(const double (&v)[D]) const {
+        double f = 0.0;
+#pragma unroll
+        for (int k = 0; k < D; ++k) f += c[k] * v[k];
+        return f;
+    }
 
     // Does the perturbed objective climb along +d?  The sign of c.d unless
     // it is within 1e-12 |c|_1 |d|_inf of zero, else of the first -d_k above
     // 1e-12 |d|_inf.  (Scales are norms, not the products' magnitudes: a
     // component of d that is zero up to rounding must not decide.)
     __device__ __forceinline__ bool prefers_up(const double (&d)[D], double dmax) const {
-        double cd = 0.0, cn = 0.0;
+        double cd = 0.0;
 #pragma unroll
-        for (int k = 0; k < D; ++k) {
-            cd += c[k] * d[k];
-            cn += __builtin_fabs(c[k]);
-        }
+        for (int k = 0; k < D; ++k) cd += c[k] * d[k];
         const double mag = cn * dmax;
         if (cd > kTolTie * mag) return true;
         if (cd < -kTolTie * mag) return false;
@@ -219,7 +222,8 @@ struct Group {
     // coordinates solve the hyperplane equations.  Kept if it lies inside
     // the remaining preferred faces and beats the best so far.
     template <int R, int Q>
-    __device__ __forceinline__ void try_start(const Row<D> (&h)[R], double (&best)[D], bool& found) const {
+    __device__ __forceinline__ void try_start(const Row<D> (&h)[R], double (&best)[D], double& fbest,
+                                              bool& found) const {
         constexpr int kU = ((1 << D) - 1) & ~Q;
         constexpr Bits<kU, R> u{};
         double A[R][R], rhs[R];
@@ -250,18 +254,21 @@ struct Group {
             const int k = u.v[t];
             if (sgn(k) * cand[k] - P.M > kTolViol * (__builtin_fabs(cand[k]) + P.M)) return;
         }
-        if (!found || better(cand, best)) {
+        const double fc = objective(cand);
+        if (!found || better(cand, fc, best, fbest)) {
             found = true;
+            fbest = fc;
 #pragma unroll
             for (int k = 0; k < D; ++k) best[k] = cand[k];
         }
     }
 
     template <int R, int Q>
-    __device__ __forceinline__ void each_start(const Row<D> (&h)[R], double (&best)[D], bool& found) const {
+    __device__ __forceinline__ void each_start(const Row<D> (&h)[R], double (&best)[D], double& fbest,
+                                               bool& found) const {
         if constexpr (Q < (1 << D)) {
-            if constexpr (popc(Q) == D - R) try_start<R, Q>(h, best, found);
-            each_start<R, Q + 1>(h, best, found);
+            if constexpr (popc(Q) == D - R) try_start<R, Q>(h, best, fbest, found);
+            each_start<R, Q + 1>(h, best, fbest, found);
         }
     }
 
@@ -274,147 +281,264 @@ struct Group {
 #pragma unroll
         for (int i = 0; i < R; ++i) h[i] = row(H[i]);
         bool found = false;
-        each_start<R, 0>(h, y, found);
+        double fbest = 0.0;
+        each_start<R, 0>(h, y, fbest, found);
         return found;
     }
 
-    // The line cut by the D - 1 hyperplanes H[0..D-1), as p + t d, by
-    // elimination with the largest pivot of each row; the column never
-    // chosen is the line's parameter (d has 1 there).  False when a
-    // hyperplane depends on the ones before it.
-    __device__ __forceinline__ bool line(double (&p)[D], double (&d)[D]) const {
-        constexpr int R = D - 1;
-        double A[R][D + 1], nrm[R];
-#pragma unroll
-        for (int i = 0; i < R; ++i) {
-            const Row<D> h = row(H[i]);
-            nrm[i] = 0.0;
+    // The plane cut by the D - 2 hyperplanes H[0..D-2), as x = q + u e + v f,
+    // by elimination with the largest pivot of each row; the two columns
+    // never chosen are u and v (e has 1 in the first, 0 in the second, f the
+    // reverse).  False when a hyperplane depends on the ones before it.
+    __device__ __forceinline__ bool plane(double (&q)[D], double (&e)[D], double (&f)[D]) const {
+        constexpr int R = D - 2;
+        if constexpr (R == 0) {
 #pragma unroll
             for (int k = 0; k < D; ++k) {
-                A[i][k] = h.a[k];
-                nrm[i] += __builtin_fabs(h.a[k]);
+                q[k] = 0.0;
+                e[k] = k == 0 ? 1.0 : 0.0;
+                f[k] = k == 1 ? 1.0 : 0.0;
             }
-            A[i][D] = h.b;
-        }
-        int used = 0, pc[R];
+            return true;
+        } else {
+            double A[R][D + 1], nrm[R];
 #pragma unroll
-        for (int i = 0; i < R; ++i) {
-            double best = -1.0, piv = 0.0;
-            int bk = 0;
+            for (int i = 0; i < R; ++i) {
+                const Row<D> h = row(H[i]);
+                nrm[i] = 0.0;
 #pragma unroll
-            for (int k = 0; k < D; ++k) {
-                const double v = __builtin_fabs(A[i][k]);
-                if (!((used >> k) & 1) && v > best) {
-                    best = v;
-                    bk = k;
-                    piv = A[i][k];
+                for (int k = 0; k < D; ++k) {
+                    A[i][k] = h.a[k];
+                    nrm[i] += __builtin_fabs(h.a[k]);
+                }
+                A[i][D] = h.b;
+            }
+            int used = 0, pc[R];
+#pragma unroll
+            for (int i = 0; i < R; ++i) {
+                double best = -1.0, piv = 0.0;
+                int bk = 0;
+#pragma unroll
+                for (int k = 0; k < D; ++k) {
+                    const double v = __builtin_fabs(A[i][k]);
+                    if (!((used >> k) & 1) && v > best) {
+                        best = v;
+                        bk = k;
+                        piv = A[i][k];
+                    }
+                }
+                if (!(best > kTolPar * nrm[i])) return false;
+                pc[i] = bk;
+                used |= 1 << bk;
+                const double inv = 1.0 / piv;
+#pragma unroll
+                for (int k = 0; k <= D; ++k) A[i][k] = k == bk ? 1.0 : A[i][k] * inv;
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    if (r == i) continue;
+                    double g = 0.0;
+#pragma unroll
+                    for (int k = 0; k < D; ++k)
+                        if (k == bk) g = A[r][k];
+#pragma unroll
+                    for (int k = 0; k <= D; ++k) A[r][k] = k == bk ? 0.0 : __builtin_fma(-g, A[i][k], A[r][k]);
                 }
             }
-            if (!(best > kTolPar * nrm[i])) return false;
-            pc[i] = bk;
-            used |= 1 << bk;
-            const double inv = 1.0 / piv;
+            const int free = ~used & ((1 << D) - 1);
+            const int c1 = __builtin_ctz(free), c2 = __builtin_ctz(free & (free - 1));
 #pragma unroll
-            for (int k = 0; k <= D; ++k) A[i][k] = k == bk ? 1.0 : A[i][k] * inv;
+            for (int k = 0; k < D; ++k) {
+                q[k] = 0.0;
+                e[k] = k == c1 ? 1.0 : 0.0;
+                f[k] = k == c2 ? 1.0 : 0.0;
+            }
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-                if (r == i) continue;
-                double f = 0.0;
+            for (int i = 0; i < R; ++i) {
+                double a1 = 0.0, a2 = 0.0;
+#pragma unroll
+                for (int k = 0; k < D; ++k) {
+                    if (k == c1) a1 = A[i][k];
+                    if (k == c2) a2 = A[i][k];
+                }
 #pragma unroll
                 for (int k = 0; k < D; ++k)
-                    if (k == bk) f = A[r][k];
-#pragma unroll
-                for (int k = 0; k <= D; ++k) A[r][k] = k == bk ? 0.0 : __builtin_fma(-f, A[i][k], A[r][k]);
+                    if (k == pc[i]) {
+                        q[k] = A[i][D];
+                        e[k] = -a1;
+                        f[k] = -a2;
+                    }
             }
+            return true;
         }
-        const int fcol = __builtin_ctz(~used & ((1 << D) - 1));
+    }
+
+    // The best point of the plane q + u e + v f inside the preferred faces
+    // (the start of the plane's LP): where two of the faces meet, inside the
+    // others, best by the perturbed objective.  False when there is none.
+    __device__ __forceinline__ bool plane_start(const double (&q)[D], const double (&e)[D], const double (&f)[D],
+                                                double (&best)[D]) const {
+        bool found = false;
+        double fbest = 0.0;
+#pragma unroll
+        for (int k1 = 0; k1 < D; ++k1)
+#pragma unroll
+            for (int k2 = k1 + 1; k2 < D; ++k2) {
+                const double det = e[k1] * f[k2] - f[k1] * e[k2];
+                const double sc = (__builtin_fabs(e[k1]) + __builtin_fabs(f[k1])) *
+                                  (__builtin_fabs(e[k2]) + __builtin_fabs(f[k2]));
+                if (!(__builtin_fabs(det) > kTolSing * sc)) continue;
+                const double r1 = sgn(k1) * P.M - q[k1], r2 = sgn(k2) * P.M - q[k2];
+                const double inv = 1.0 / det;
+                const double u = (r1 * f[k2] - f[k1] * r2) * inv, v = (e[k1] * r2 - r1 * e[k2]) * inv;
+                double cand[D];
+                bool inside = true;
+#pragma unroll
+                for (int k = 0; k < D; ++k) {
+                    cand[k] = k == k1 || k == k2 ? sgn(k) * P.M : __builtin_fma(v, f[k], __builtin_fma(u, e[k], q[k]));
+                    if (k != k1 && k != k2)
+                        inside = inside && !(sgn(k) * cand[k] - P.M > kTolViol * (__builtin_fabs(cand[k]) + P.M));
+                }
+                if (!inside) continue;
+                const double fc = objective(cand);
+                if (!found || better(cand, fc, best, fbest)) {
+                    found = true;
+                    fbest = fc;
+#pragma unroll
+                    for (int k = 0; k < D; ++k) best[k] = cand[k];
+                }
+            }
+        return found;
+    }
+
+    // The line where row h's hyperplane meets the plane q + u e + v f, as
+    // p + t d: with alpha = a.e, beta = a.f, gamma = b - a.q the line is
+    // alpha u + beta v = gamma, solved for the variable with the larger
+    // coefficient.  False when the row is parallel to the plane (its normal
+    // depends on the plane's hyperplanes).
+    __device__ __forceinline__ bool line_in_plane(const double (&q)[D], const double (&e)[D], const double (&f)[D],
+                                                  const Row<D>& h, double (&p)[D], double (&d)[D]) const {
+        double al = 0.0, be = 0.0, aq = 0.0, an = 0.0, bmax = 0.0;
 #pragma unroll
         for (int k = 0; k < D; ++k) {
-            d[k] = k == fcol ? 1.0 : 0.0;
-            p[k] = 0.0;
+            al += h.a[k] * e[k];
+            be += h.a[k] * f[k];
+            aq += h.a[k] * q[k];
+            an += __builtin_fabs(h.a[k]);
+            bmax = __builtin_fmax(bmax, __builtin_fmax(__builtin_fabs(e[k]), __builtin_fabs(f[k])));
         }
+        const double ga = h.b - aq;
+        const bool ue = __builtin_fabs(al) >= __builtin_fabs(be);
+        const double piv = ue ? al : be, oth = ue ? be : al;
+        if (!(__builtin_fabs(piv) > kTolPar * an * bmax)) return false;
+        const double r = 1.0 / piv, t0 = ga * r, w = oth * r;
 #pragma unroll
-        for (int i = 0; i < R; ++i) {
-            double af = 0.0;
-#pragma unroll
-            for (int k = 0; k < D; ++k)
-                if (k == fcol) af = A[i][k];
-#pragma unroll
-            for (int k = 0; k < D; ++k)
-                if (k == pc[i]) {
-                    d[k] = -af;
-                    p[k] = A[i][D];
-                }
+        for (int k = 0; k < D; ++k) {
+            const double pv = ue ? e[k] : f[k], ov = ue ? f[k] : e[k];
+            p[k] = __builtin_fma(t0, pv, q[k]);
+            d[k] = __builtin_fma(-w, pv, ov);
         }
         return true;
     }
 
+    // Level 2: on the plane q + u e + v f (x its start), scan the virtual rows
+    // [first, lim) against x; each violated row starts the 1D LP on the line
+    // where it meets the plane, over the rows before it.
+    __device__ void scan_plane(const double (&q)[D], const double (&e)[D], const double (&f)[D], int first,
+                               int lim) {
+        int cur = first;
+        while (cur < lim) {
+            const int j = cur + gl;
+            Row<D> r = row(j < lim ? j : 0);
+            const bool viol = j < lim && violates(r, x);
+            const uint64_t bal = __ballot(viol) & gmask;
+            if (bal == 0) {
+                cur += G;
+                continue;
+            }
+            const int src = __builtin_ctzll(bal);
+            const int hv = cur + (src - gbase);
+            // the violated row, from the lane that tested it
+#pragma unroll
+            for (int k = 0; k < D; ++k) r.a[k] = __shfl(r.a[k], src);
+            r.b = __shfl(r.b, src);
+            double p[D], d[D];
+            if (!line_in_plane(q, e, f, r, p, d)) {
+                status = kInfeasible;
+                return;
+            }
+            lp1(p, d, hv);
+            if (status != kAlive) return;
+            cur = hv + 1;
+        }
+    }
+
     // The 1D LP on p + t d over the virtual rows [0, lim): each lane keeps
-    // the tightest bound of each side over its rows; the bound the objective
-    // climbs towards is reduced over the group; infeasible when a row parallel
-    // to the line excludes it or the other side's tightest row is violated at
-    // the new vertex.  On success x is that vertex.
+    // the tightest bound of each side over its rows (for the side the
+    // objective does not climb towards, with that row's s = a.d, n = b - a.p
+    // and scales); the climbing side's bound is reduced over the group;
+    // infeasible when a row parallel to the line excludes it or the other
+    // side's tightest row is violated at the new vertex (its residual there
+    // is s tau - n).  On success x is that vertex.
     __device__ void lp1(const double (&p)[D], const double (&d)[D], int lim) {
         double dmax = 0.0;
 #pragma unroll
         for (int k = 0; k < D; ++k) dmax = __builtin_fmax(dmax, __builtin_fabs(d[k]));
         const bool up = prefers_up(d, dmax);
-        double hi = __builtin_huge_val(), lo = -__builtin_huge_val();
-        int ihi = -1, ilo = -1;
+        double best = __builtin_huge_val(), other = -__builtin_huge_val();  // in the climbing direction
+        double os = 0.0, on = 0.0, oan = 0.0, oapa = 0.0;
         bool par = false;
         for (int g = gl; g < lim; g += G) {
             const Row<D> r = row(g);
-            double s = 0.0, an = 0.0, ap = 0.0, apa = __builtin_fabs(r.b);
+            double sv = 0.0, an = 0.0, ap = 0.0, apa = __builtin_fabs(r.b);
 #pragma unroll
             for (int k = 0; k < D; ++k) {
-                s += r.a[k] * d[k];
+                sv += r.a[k] * d[k];
                 an += __builtin_fabs(r.a[k]);
                 const double q = r.a[k] * p[k];
                 ap += q;
                 apa += __builtin_fabs(q);
             }
-            const double sa = an * dmax;
+            const double tol = kTolPar * an * dmax;
             const double n = r.b - ap;
-            if (s > kTolPar * sa) {
-                const double t = n / s;
-                if (t < hi) {
-                    hi = t;
-                    ihi = g;
-                }
-            } else if (s < -kTolPar * sa) {
-                const double t = n / s;
-                if (t > lo) {
-                    lo = t;
-                    ilo = g;
+            if (sv > tol || sv < -tol) {
+                const double t = n / sv;
+                // in the climbing direction: a bound ahead (s > 0 when up)
+                // caps the climb, a bound behind is the other side
+                const bool ahead = (sv > 0.0) == up;
+                const double tc = up ? t : -t;
+                if (ahead) {
+                    best = __builtin_fmin(best, tc);
+                } else if (tc > other) {
+                    other = tc;
+                    os = sv;
+                    on = n;
+                    oan = an;
+                    oapa = apa;
                 }
             } else {
                 par |= n < -kTolViol * apa;
             }
         }
-        const double kmin = rgbd::group_min_d<LG>(up ? hi : -lo);
+        const double kmin = rgbd::group_min_d<LG>(best);
         if (!(kmin < __builtin_huge_val())) {  // unreachable: the preferred faces bound the climb
             status = kInvalid;
             return;
         }
         const double tau = up ? kmin : -kmin;
-        double xn[D];
-#pragma unroll
-        for (int k = 0; k < D; ++k) xn[k] = __builtin_fma(tau, d[k], p[k]);
-        bool crosses = false;
-        const int io = up ? ilo : ihi;
-        if (io >= 0 && (up ? lo > tau : hi < tau)) crosses = violates(row(io), xn);
+        const bool crosses = other > kmin &&
+                             __builtin_fma(os, tau, -on) > kTolViol * (oapa + __builtin_fabs(tau) * oan * dmax);
         if ((__ballot(par || crosses) & gmask) != 0) {
             status = kInfeasible;
             return;
         }
 #pragma unroll
-        for (int k = 0; k < D; ++k) x[k] = xn[k];
+        for (int k = 0; k < D; ++k) x[k] = __builtin_fma(tau, d[k], p[k]);
     }
 
     template <int K>
     __device__ void descend(int hv);
 
-    // Level K (the current subspace has dimension K, 2 <= K < D): scan the
+    // Level K (the current subspace has dimension K, 3 <= K < D): scan the
     // virtual rows [first, lim) against x; each violated row starts level
     // K - 1 on its hyperplane.
     template <int K>
@@ -443,13 +567,28 @@ template <int D, int LG>
 template <int K>
 __device__ void Group<D, LG>::descend(int hv) {
     H[D - K] = hv;
-    if constexpr (K == 2) {
-        double p[D], d[D];
-        if (!line(p, d)) {
+    if constexpr (K == 2) {  // D == 2: the plane is the whole space
+        double q[D], e[D], f[D], p[D], d[D];
+        plane(q, e, f);
+        if (!line_in_plane(q, e, f, row(hv), p, d)) {
             status = kInfeasible;
             return;
         }
         lp1(p, d, hv);
+    } else if constexpr (K == 3) {
+        double q[D], e[D], f[D];
+        if (!plane(q, e, f)) {
+            status = kInfeasible;
+            return;
+        }
+        double y[D];
+        if (!plane_start(q, e, f, y)) {
+            status = kInfeasible;
+            return;
+        }
+#pragma unroll
+        for (int k = 0; k < D; ++k) x[k] = y[k];
+        scan_plane(q, e, f, D, hv);
     } else {
         double y[D];
         if (!subspace_start<D - K + 1>(y)) {
@@ -498,6 +637,9 @@ __device__ void solve_group(const ProblemN& P, int64_t lp) {
         S.x[k] = S.sgn(k) * P.M;
         S.H[k] = 0;
     }
+    S.cn = 0.0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) S.cn += __builtin_fabs(S.c[k]);
     S.status = ok ? kAlive : kInvalid;
     bool bad = false;
     int cur = 2 * D;  // the box faces hold at the starting corner
@@ -549,8 +691,15 @@ __device__ void solve_group(const ProblemN& P, int64_t lp) {
     }
 }
 
+// Waves per SIMD the register allocation aims for: three for n = 4 (at most
+// 168 VGPRs, a few spilled on the rare paths) hide more of the dependent FP64
+// chains than two at ~180-220; for n = 5 the spills cost more than the third
+// wave gains, so it keeps all the registers it needs.
+template <int D>
+constexpr int kWavesPerEu = D == 4 ? 3 : 1;
+
 template <int D, int G>
-__global__ __launch_bounds__(256) void k_seidelN(ProblemN P) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEu<D>))) void k_seidelN(ProblemN P) {
     constexpr int LG = G == 4 ? 2 : G == 8 ? 3 : G == 16 ? 4 : G == 32 ? 5 : 6;
     const int64_t q = (int64_t)blockIdx.x * (256 / G) + threadIdx.x / G;
     solve_group<D, LG>(P, q < P.num_lps ? q : -1);
@@ -577,7 +726,7 @@ extern "C" rgb_err_t rgb_solven_batch(rgb_ctx_t* ctx, int32_t dim, int64_t num_l
     if (!ctx || num_lps < 0 || num_constraints < 0) return RGB_ERR_INVALID_ARG;
     if (dim < 2 || dim > rgbn::kMaxDim) return RGB_ERR_INVALID_ARG;
     if (!(box > 0.0) || !__builtin_isfinite(box)) return RGB_ERR_INVALID_ARG;
-    const int G = lanes_per_lp == 0 ? 16 : lanes_per_lp;
+    const int G = lanes_per_lp != 0 ? lanes_per_lp : dim == 5 ? 8 : 16;
     if (G != 4 && G != 8 && G != 16 && G != 32 && G != 64) return RGB_ERR_INVALID_ARG;
     if (num_lps > (int64_t(1) << 31) - 1) return RGB_ERR_TOO_LARGE;
     if (num_lps == 0) return RGB_OK;

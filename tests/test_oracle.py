@@ -408,7 +408,7 @@ def test_margin_and_range_pins_catch_planted_mistakes(oracle_lib, mi):
         open(c, "w").write(src.replace(old, new))
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fPIC", "-shared", "-o", so, c, "-lm"])
         lib = ctypes.CDLL(so)
-        saved = oracle_lib._lib
+        saved = oracle_lib._load()
         lib.rgb_oracle_solve_range.argtypes = saved.rgb_oracle_solve_range.argtypes
         oracle_lib._lib = lib
         try:

@@ -281,7 +281,10 @@ typedef struct {
     int32_t pending, in_flight;    /* requests queued / admitted and not yet finished */
 } rgb_server_stats_t;
 
-/* Start a server on ctx's device (ctx itself is not used afterwards).
+/* Start a server on ctx's device (ctx itself is not used afterwards).  The
+ * pinned host rings and staging buffers are written once here, so that the
+ * first requests do not pay the first touch of their pages (creation takes
+ * about as long as a host memset of host_ring_mib).
  * Errors: INVALID_ARG (bad option), OOM (arena or pinned buffers), DEVICE. */
 rgb_err_t rgb_server_create(rgb_ctx_t* ctx, const rgb_server_opts_t* opts, rgb_server_t** out);
 

@@ -343,6 +343,11 @@ rgb_err_t rgb_server_create(rgb_ctx_t* ctx, const rgb_server_opts_t* opts, rgb_s
         rgb_server_destroy(s);
         return RGB_ERR_DEVICE;
     }
+    // Touch every page of the rings once now: the first host write to a page
+    // of this memory is several times slower than later ones, and without
+    // this the first pass of requests through the rings (a whole ring's worth
+    // of submits) pays it inside the submit calls.
+    std::memset(s->ring_mem, 0, (size_t)n_rows * 12 + (size_t)n_lps * 16);
     s->r_end = reinterpret_cast<int64_t*>(s->ring_mem);
     s->r_cx = reinterpret_cast<float*>(s->r_end + n_lps);
     s->r_cy = s->r_cx + n_lps;
@@ -367,6 +372,7 @@ rgb_err_t rgb_server_create(rgb_ctx_t* ctx, const rgb_server_opts_t* opts, rgb_s
             rgb_server_destroy(s);
             return RGB_ERR_DEVICE;
         }
+        std::memset(sl.pinned, 0, sl.out_at + 3 * Layout::al(4 * cap));
     }
     s->thr = std::thread([s] { s->run(); });
     *out = s;

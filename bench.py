@@ -101,6 +101,14 @@ def served_leg(rgb, gen, n_requests, loads, fifo_requests=1500, threads=4, pool_
                 "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
                 "max_ms": float(lat.max())}
 
+    # The submitting threads are Python: a full garbage collection inside one
+    # of them stalls its submits for tens of ms (measured: one 51 ms submit
+    # call in the first timed stream, none later), which is the harness, not
+    # the server.  Everything allocated so far is frozen out of collection for
+    # the timed runs.
+    import gc
+    gc.collect()
+    gc.freeze()
     served = rgb.Server(n_streams=4, max_batch_lps=16384, hbm_budget=4 << 30, host_ring_mib=1024)
     fifo = rgb.Server(n_streams=1, one_request_per_batch=True, variant="plain", hbm_budget=4 << 30,
                       host_ring_mib=1024)
@@ -127,6 +135,7 @@ def served_leg(rgb, gen, n_requests, loads, fifo_requests=1500, threads=4, pool_
     out["plain_fifo"]["trace"] = f"the first {n} requests of the {loads[-1]}x stream"
     served.close()
     fifo.close()
+    gc.unfreeze()
     return out
 
 

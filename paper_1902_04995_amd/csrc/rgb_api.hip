@@ -355,6 +355,10 @@ rgb_err_t enqueue(rgb_ctx_t* ctx, const rgb::Problem& P, int variant, const rgb_
 }  // namespace
 
 int rgb::ctx_device(const rgb_ctx* ctx) { return ctx->device; }
+bool rgb::reserve_workspace(rgb_ctx* ctx, void* stream, int64_t num_lps) {
+    rgb::Workspace w;
+    return stream_workspace(ctx, stream, num_lps, w) == RGB_OK;
+}
 rgb::HostPath*& rgb::ctx_host_path(rgb_ctx* ctx) { return ctx->host; }
 
 extern "C" {

@@ -73,6 +73,10 @@ int table_save(const char* path, const std::string& device_key, const TableEntry
 
 // Device of a context (for the server, which only sees the opaque type).
 int ctx_device(const struct ::rgb_ctx* ctx);
+// Give the context's workspace for solves on `stream` room for num_lps LPs
+// now (a later larger solve on that stream would otherwise reallocate it,
+// synchronising the stream).  False on failure.
+bool reserve_workspace(struct ::rgb_ctx* ctx, void* stream, int64_t num_lps);
 
 // Copy `bytes` bytes with a kernel on `stream` (not a DMA-engine copy), so
 // that the copy, the kernels around it and a completion event recorded after

@@ -373,6 +373,12 @@ rgb_err_t rgb_server_create(rgb_ctx_t* ctx, const rgb_server_opts_t* opts, rgb_s
             return RGB_ERR_DEVICE;
         }
         std::memset(sl.pinned, 0, sl.out_at + 3 * Layout::al(4 * cap));
+        // the solver's workspace for this stream at its largest micro-batch
+        // now, not by reallocation (which synchronises) while serving
+        if (!rgb::reserve_workspace(s->ctx, sl.stream, cap)) {
+            rgb_server_destroy(s);
+            return RGB_ERR_OOM;
+        }
     }
     s->thr = std::thread([s] { s->run(); });
     *out = s;

@@ -250,3 +250,45 @@ def test_seidelN_lp_over_row_limit(rgb, oracle_lib):
         assert len(bs) + len(bx) == 0, (g, st[1], xv[1], ref["status"], ref["x"])
     del a, b
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("n", [4, 5])
+def test_seidelN_graph_replay_and_side_stream(rgb, n):
+    """The n-dimensional solve allocates nothing, so it can be captured in a
+    HIP graph: replays with eager work and synchronisations between them, and
+    a launch on a non-default stream, give the eager solve's bits."""
+    import torch
+    bt = genn.concat_n([genn.uniform_n_batch(n, 600, 10 * n, seed=80 + n),
+                        genn.tiny_integer_n_batch(n, 600, m_max=2 * n + 2, K=2, seed=81 + n, box=1.0e4)])
+    dev = rgb.DeviceBatchN(bt, "cuda:0")
+    x0, s0 = dev.solve()
+    torch.cuda.synchronize()
+    ref = (x0.cpu().numpy(), s0.cpu().numpy())
+    other = rgb.DeviceBatchN(genn.uniform_n_batch(n, 300, 8 * n, seed=82 + n), "cuda:0")
+    ox, os_ = other.solve()
+    torch.cuda.synchronize()
+    other_ref = (ox.cpu().numpy(), os_.cpu().numpy())
+    out = (torch.empty((n, bt.num_lps), dtype=torch.float32, device="cuda"),
+           torch.empty(bt.num_lps, dtype=torch.int32, device="cuda"))
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        dev.solve(out=out, stream=side)
+    side.synchronize()
+    assert np.array_equal(out[0].cpu().numpy().view(np.int32), ref[0].view(np.int32))
+    assert np.array_equal(out[1].cpu().numpy(), ref[1])
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        dev.solve(out=out, stream=torch.cuda.current_stream())
+    for rep in range(3):
+        out[0].fill_(7.0)
+        out[1].fill_(9)
+        ex, es = other.solve()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(out[0].cpu().numpy().view(np.int32), ref[0].view(np.int32)), rep
+        assert np.array_equal(out[1].cpu().numpy(), ref[1]), rep
+        assert np.array_equal(ex.cpu().numpy().view(np.int32), other_ref[0].view(np.int32)), rep
+        assert np.array_equal(es.cpu().numpy(), other_ref[1]), rep
+    del g

@@ -33,10 +33,10 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, public spec
 # Keyed by (kernel, workload) and valid only for the kernel sources whose
 # digest is recorded: after any kernel change the figure is reported as null.
 MEASURED_TRAFFIC = {
-    "sources": "b9edc17743b7aa39",
-    ('k_group<16>', 'uniform'): 888390389,
-    ('k_group<8>', 'crowd'): 414046292,
-    ('k_binned', 'uneven'): 7513552220,
+    "sources": "2aed40b082c422ac",
+    ('k_group<16>', 'uniform'): 889036578,
+    ('k_group<8>', 'crowd'): 414672487,
+    ('k_binned', 'uneven'): 7440997698,
 }
 
 

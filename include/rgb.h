@@ -431,7 +431,8 @@ rgb_err_t rgb_reduce_bench_run(int32_t method, int32_t contention, int64_t n, co
  * ev_end: optional hipEvent_t recorded on `stream` around the kernel.
  * Enqueued on `stream` (0 = null stream) on ctx's device; returns before the
  * solve completes.  Errors (synchronous, nothing enqueued): INVALID_ARG for
- * a null context or pointer, negative sizes, box not finite and positive or
+ * a null context or pointer, negative sizes, box not positive or above the
+ * largest FP32 value (x is written in FP32) or
  * an unsupported lanes_per_lp; TOO_LARGE above 2^31 - 1 LPs; DEVICE when
  * the launch fails.
  * ------------------------------------------------------------------------- */
@@ -472,7 +473,8 @@ rgb_err_t rgb_solve3_batch(rgb_ctx_t* ctx, int64_t num_lps, int64_t num_constrai
  * Enqueued on `stream` (0 = null stream) on ctx's device; returns before the
  * solve completes.  Errors (synchronous, nothing enqueued): INVALID_ARG for
  * a null context or pointer, negative sizes, dim outside 2..5, box not
- * finite and positive or an unsupported lanes_per_lp; TOO_LARGE above
+ * positive or above the largest FP32 value (x is written in FP32) or an
+ * unsupported lanes_per_lp; TOO_LARGE above
  * 2^31 - 1 LPs; DEVICE when the launch fails.
  * ------------------------------------------------------------------------- */
 rgb_err_t rgb_solven_batch(rgb_ctx_t* ctx, int32_t dim, int64_t num_lps, int64_t num_constraints,

@@ -725,7 +725,9 @@ extern "C" rgb_err_t rgb_solven_batch(rgb_ctx_t* ctx, int32_t dim, int64_t num_l
                                       void* stream, void* ev_begin, void* ev_end) {
     if (!ctx || num_lps < 0 || num_constraints < 0) return RGB_ERR_INVALID_ARG;
     if (dim < 2 || dim > rgbn::kMaxDim) return RGB_ERR_INVALID_ARG;
-    if (!(box > 0.0) || !__builtin_isfinite(box)) return RGB_ERR_INVALID_ARG;
+    // the box must be positive and an FP32 value: x is written in FP32, and an
+    // optimum on a face of a larger box would not be
+    if (!(box > 0.0) || !(box <= 3.4028234663852886e38)) return RGB_ERR_INVALID_ARG;
     const int G = lanes_per_lp != 0 ? lanes_per_lp : dim == 5 ? 8 : 16;
     if (G != 4 && G != 8 && G != 16 && G != 32 && G != 64) return RGB_ERR_INVALID_ARG;
     if (num_lps > (int64_t(1) << 31) - 1) return RGB_ERR_TOO_LARGE;

@@ -137,7 +137,7 @@ def test_seidel3_edges(rgb, oracle_lib):
     s_ = s_.cpu().numpy()
     assert s_[2] == INVALID and s_[3] == INVALID and s_[6] == INVALID and s_[7] == INVALID
     # argument errors are synchronous and enqueue nothing
-    for box in (0.0, -1.0, float("inf"), float("nan")):
+    for box in (0.0, -1.0, float("inf"), float("nan"), 1e39):
         with pytest.raises(rgb.RgbError):
             rgb.solve3_batch(dev.offsets, dev.ax, dev.ay, dev.az, dev.b, dev.cx, dev.cy, dev.cz, box)
     with pytest.raises(rgb.RgbError):

@@ -155,7 +155,7 @@ def test_seidelN_edges(rgb, oracle_lib):
         s_ = s_.cpu().numpy()
         assert s_[2] == INVALID and s_[3] == INVALID and s_[6] == INVALID and s_[7] == INVALID
         # argument errors are synchronous and enqueue nothing
-        for box in (0.0, -1.0, float("inf"), float("nan")):
+        for box in (0.0, -1.0, float("inf"), float("nan"), 1e39):
             with pytest.raises(rgb.RgbError):
                 rgb.solven_batch(dev.offsets, dev.a, dev.b, dev.c, box)
         with pytest.raises(rgb.RgbError):

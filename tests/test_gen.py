@@ -38,7 +38,7 @@ def test_special_rows_are_uniformly_placed():
 
 
 def test_uneven_log_uniform():
-    bt = gen.uneven_batch(20000, 8, 8192, seed=2, infeasible_frac=0.0, unbounded_frac=0.0)
+    bt = gen.uneven_batch(4000, 8, 8192, seed=2, infeasible_frac=0.0, unbounded_frac=0.0)
     m = bt.sizes() - 4
     assert m.min() >= 8 and m.max() <= 8192
     lm = np.log(m)

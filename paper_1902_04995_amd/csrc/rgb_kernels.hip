@@ -231,13 +231,57 @@ __device__ __forceinline__ void settle_1dlp(LpState& st, const Rows& R, int v, f
     else move_on_line(st, v, L, hi, lo, prefers_up(L, cx, cy));
 }
 
+// Where the rows attaining the last 1D LP's bound were seen (kept by the
+// cached group path): `mine` has the bit of every lane whose own bound equals
+// its group's on that 1D LP, and such a lane's `rec` names the first step of
+// its work-unit loops that reached that bound: a row below `from` = min(cs,
+// rg) starts a step of the LDS loop, a row below cs a step of the memory loop
+// (U rows rec + k G, clamped below those bounds as the loops clamp them), any
+// other row is one of the chunk's own rows.  cs is the chunk holding the
+// line's row, C rows per chunk.  A group with no bit in `mine` has no record.
+struct FindHint {
+    uint64_t mine = 0;
+    int rec = kNoIdx;
+    int C = 1, rg = 0, U = 4;
+};
+
+// Smallest row attaining bound st.sig on line L from the record: each lane
+// holding the bound tests the rows of its recorded step again (the lane took
+// its rows in increasing order and kept the first step that reached its
+// bound, so the step holds the lane's smallest attaining row, or a clamped
+// repeat of a row no larger than its later ones), and the group takes the
+// smallest hit.  Every attaining row's own lane holds the bound, so the
+// result is the row group_find would return, from U rows instead of st.l.
+template <class Rows>
+__device__ __forceinline__ int recorded_find(const Rows& R, const LpState& st, const Line& L, const FindHint& hint,
+                                             const GroupLanes& ln) {
+    int f = kNoIdx;
+    if ((hint.mine >> __lane_id()) & 1ull) {
+        const int G = ln.step();
+        const int cs = st.l & -hint.C;
+        const int from = cs < hint.rg ? cs : hint.rg;
+        const bool own = hint.rec >= cs;
+        const int bound = hint.rec < from ? from : cs;
+        for (int k = 0; k < (own ? 1 : hint.U); ++k) {
+            int hk = hint.rec + k * G;
+            hk = own || hk < bound ? hk : bound - 1;
+            float D;
+            const float s = wu_sigma(R.x(hk), R.y(hk), R.c(hk), L, D);
+            const bool hit = (st.up ? D > 0.0f : D < 0.0f) && s == st.sig;
+            f = hit && hk < f ? hk : f;
+        }
+    }
+    return ln.imin(f);
+}
+
 // End of one LP on its group: an LP that died early still gets its remaining
-// rows checked for non-finite values, a vertex gets its second defining row,
-// and the group's first lane stores the result.
+// rows checked for non-finite values, a vertex gets its second defining row
+// (from the record when the group has one, else by a pass over the rows below
+// its line), and the group's first lane stores the result.
 template <bool WIDE>
 __device__ __forceinline__ void finish_group(const Problem& P, int64_t lp, int64_t start, const RowRef<WIDE>& R,
                                              LpState& st, int cur, int m, bool bad, int n1d, int gl, int lg,
-                                             uint64_t gmask) {
+                                             uint64_t gmask, const FindHint& hint = FindHint{}) {
     if (lp >= 0 && st.kind == kDead && st.dead_status == kInfeasible)
         for (int idx = cur + gl; idx < m; idx += (1 << lg)) bad |= !finite3(R.x(idx), R.y(idx), R.c(idx));
     if ((__ballot(bad) & gmask) != 0) set_dead(st, kInvalid);
@@ -246,7 +290,8 @@ __device__ __forceinline__ void finish_group(const Problem& P, int64_t lp, int64
         if (st.kind == kPoint) {
             Line L;
             make_line(L, R.x(st.l), R.y(st.l), R.c(st.l));
-            h = group_find(R, st.l, L, st.sig, st.up, GroupLanes{gl, lg, gmask});
+            const GroupLanes ln{gl, lg, gmask};
+            h = (hint.mine & gmask) != 0 ? recorded_find(R, st, L, hint, ln) : group_find(R, st.l, L, st.sig, st.up, ln);
             if (h == kNoIdx) h = st.l;  // cannot happen (the bound came from these bits); x is NaN then
         }
     }
@@ -383,9 +428,10 @@ __device__ __forceinline__ void load_chunk(Chunk<SR>& ch, const Rows& R, int c0,
 // on the leading rows (Seidel's order makes row h's expected re-reads about
 // 2 ln(m / h)).  Only the wave's own lanes touch its part of LDS, and the LDS
 // executes one wave's accesses in order, so no barrier is needed.
-template <int LGC, bool WIDE, bool EXACT = false, int SR = 1, int U = 4, int CACHE = 0>
+template <int LGC, bool WIDE, bool EXACT = false, int SR = 1, int U = 4, int CACHE = 0, bool TRACK = false>
 __device__ __forceinline__ void solve_group(const Problem& P, int64_t lp, int lg_rt = 0, float* lds = nullptr) {
     static_assert(SR >= 1 && U >= 4 && U % 4 == 0, "scan rows and work units per lane");
+    static_assert(!TRACK || CACHE > 0, "the record is kept by the cached path");
     const int lg = LGC >= 0 ? LGC : lg_rt;
     const int G = 1 << lg;
     const int C = SR * G;  // rows per chunk
@@ -420,6 +466,15 @@ __device__ __forceinline__ void solve_group(const Problem& P, int64_t lp, int lg
     float* const kx = CACHE ? lds + (lane >> lg) * rg : nullptr;
     float* const ky = CACHE ? kx + CACHE : nullptr;
     float* const kc = CACHE ? kx + 2 * CACHE : nullptr;
+    // With TRACK, each 1D LP also records where its bound was reached
+    // (FindHint), so the end of the LP needs no pass over the rows below its
+    // line.  The record costs a few instructions per work-unit step and a
+    // register: it pays on large LPs, whose last line lies thousands of rows
+    // in and whose rows are no longer in any cache by the end.
+    FindHint hint;
+    hint.C = C;
+    hint.rg = rg;
+    hint.U = U;
 
     while (__ballot(!done) != 0) {
         if (fresh && !done) {  // a non-finite row anywhere makes the LP INVALID
@@ -512,6 +567,10 @@ __device__ __forceinline__ void solve_group(const Problem& P, int64_t lp, int lg
                 float hi = __builtin_huge_valf(), lo = -__builtin_huge_valf(), chk = 0.0f;
                 // rows below the chunk: the leading ones from LDS, the rest from memory
                 int from = 0;
+                // the first step at which this lane's bound on the side c
+                // climbs towards reached its value (a step's first row)
+                const bool up = prefers_up(L, cx, cy);
+                int rc = kNoIdx;
                 if constexpr (CACHE > 0) {
                     from = cs < rg ? cs : rg;
                     for (int h = gl; h < from; h += U * G) {
@@ -524,11 +583,13 @@ __device__ __forceinline__ void solve_group(const Problem& P, int64_t lp, int lg
                             y[k] = ky[hk];
                             c[k] = kc[hk];
                         }
+                        const float h0 = hi, l0 = lo;
 #pragma unroll
                         for (int k = 0; k < U; k += 4)
                             work_units4(*reinterpret_cast<const float(*)[4]>(x + k),
                                         *reinterpret_cast<const float(*)[4]>(y + k),
                                         *reinterpret_cast<const float(*)[4]>(c + k), L, hi, lo, chk);
+                        if constexpr (TRACK) rc = (up ? hi < h0 : lo > l0) ? h : rc;
                     }
                     for (int h = from + gl; h < cs; h += U * G) {
                         float x[U], y[U], c[U];
@@ -540,11 +601,13 @@ __device__ __forceinline__ void solve_group(const Problem& P, int64_t lp, int lg
                             y[k] = R.y(hk);
                             c[k] = R.c(hk);
                         }
+                        const float h0 = hi, l0 = lo;
 #pragma unroll
                         for (int k = 0; k < U; k += 4)
                             work_units4(*reinterpret_cast<const float(*)[4]>(x + k),
                                         *reinterpret_cast<const float(*)[4]>(y + k),
                                         *reinterpret_cast<const float(*)[4]>(c + k), L, hi, lo, chk);
+                        if constexpr (TRACK) rc = (up ? hi < h0 : lo > l0) ? h : rc;
                     }
                 } else if (cs > 2 * G) {
                     for (int h = gl; h < cs; h += U * G) {
@@ -568,16 +631,31 @@ __device__ __forceinline__ void solve_group(const Problem& P, int64_t lp, int lg
                 }
                 // the chunk's rows below v, from the registers
 #pragma unroll
-                for (int k = 0; k < SR; ++k)
-                    if (cs + gl + k * G < v) work_unit(cur.x[k], cur.y[k], cur.c[k], L, hi, lo, chk);
+                for (int k = 0; k < SR; ++k) {
+                    const int idx = cs + gl + k * G;
+                    if (idx < v) {
+                        const float h0 = hi, l0 = lo;
+                        work_unit(cur.x[k], cur.y[k], cur.c[k], L, hi, lo, chk);
+                        if constexpr (TRACK) rc = (up ? hi < h0 : lo > l0) ? idx : rc;
+                    }
+                }
                 settle_group<EXACT>(st, R, v, hi, lo, chk, L, cx, cy, GroupLanes{gl, lg, gmask});
+                if constexpr (TRACK) {
+                    // a lane holds the bound when the 1D LP ended at a vertex
+                    // reached by the fast pass (no lane flagged its sum) and
+                    // its own bound is the group's
+                    const bool flagged = (__ballot(!__builtin_isfinite(chk)) & gmask) != 0;
+                    const bool holds = !flagged && st.kind == kPoint && (up ? hi : -lo) == (up ? st.sig : -st.sig);
+                    hint.mine = (hint.mine & ~__ballot(true)) | __ballot(holds);
+                    hint.rec = rc;
+                }
             }
             pos = v + 1;
             if (pos >= m || st.kind == kDead) done = true;
         }
     }
     // rows of later chunks are checked for non-finite values by finish_group
-    finish_group(P, lp, start, R, st, cs + C < m ? cs + C : m, m, false, n1d, gl, lg, gmask);
+    finish_group(P, lp, start, R, st, cs + C < m ? cs + C : m, m, false, n1d, gl, lg, gmask, hint);
 }
 
 // Scan rows per lane by group width 2^lg: a 64-lane group tests 256 rows per
@@ -595,7 +673,15 @@ constexpr int kCacheBinned = 448;
 
 // Eight waves per SIMD (at most 64 VGPRs, a few spilled at G >= 16): the
 // scan and the work units wait on memory, and more waves hide more of it.
-template <int G, bool WIDE>
+// The group kernel records the 1D-LP bound steps (TRACK of solve_group) when
+// its LPs average more than kTrackRows rows and it runs 32 or 64 lanes per
+// LP: below, the rows a find re-reads are still cached and the record's
+// instructions cost more than the find (measured on MI355X).
+constexpr int kTrackRows = 2048;
+constexpr int kTrackLg = 5;
+constexpr bool kPersistTrack = false;
+
+template <int G, bool WIDE, bool TRACK = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_group(Problem P) {
     constexpr int LPS_PER_BLOCK = 256 / G;
     int64_t q = (int64_t)blockIdx.x * LPS_PER_BLOCK + threadIdx.x / G;
@@ -603,7 +689,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
     if (q < P.num_lps) lp = P.order ? (int64_t)P.order[q] : q;
     constexpr int LG = G == 4 ? 2 : G == 8 ? 3 : G == 16 ? 4 : G == 32 ? 5 : 6;
     __shared__ float cache[4][kCacheGroup ? 3 * kCacheGroup : 1];
-    solve_group<LG, WIDE, false, scan_rows(LG), 4, kCacheGroup>(P, lp, 0, cache[threadIdx.x >> 6]);
+    solve_group<LG, WIDE, false, scan_rows(LG), 4, kCacheGroup, TRACK>(P, lp, 0, cache[threadIdx.x >> 6]);
 }
 
 // Fix-up pass after every solve: each wave looks at 64 statuses and solves
@@ -1001,7 +1087,7 @@ __device__ __forceinline__ int sub_batch_slot(const QueueHeader& Q, int k) {
 
 // Solve sub-batch k (class slot j) of the queue: 64/G LPs of one class,
 // G = 2^lg with lg = Q.lg[j] (fixed at compile time when LGC >= 0).
-template <int LGC, bool WIDE>
+template <int LGC, bool WIDE, bool TRACK = false>
 __device__ __forceinline__ void run_sub_batch(const Problem& P, const Workspace& W, const QueueHeader& Q, int k,
                                               int j, float* lds) {
     const int lg = LGC >= 0 ? LGC : Q.lg[j];
@@ -1010,11 +1096,12 @@ __device__ __forceinline__ void run_sub_batch(const Problem& P, const Workspace&
     int q = first + (__lane_id() >> lg);
     int64_t lp = q < Q.e_end[j] ? (int64_t)W.order[q] : -1;
     if (lp >= P.num_lps) lp = -1;  // never read outside the batch, whatever the queue holds
-    solve_group<LGC, WIDE, false, LGC >= 0 ? scan_rows(LGC) : 1, 4, kCacheBinned>(P, lp, lg, lds);
+    solve_group<LGC, WIDE, false, LGC >= 0 ? scan_rows(LGC) : 1, 4, kCacheBinned, TRACK>(P, lp, lg, lds);
 }
 
 // Sub-batch k of the queue with the group width of its class fixed at compile
-// time (the same code as the group kernel's for that width).
+// time (the same code as the group kernel's for that width), recording the
+// bound steps where the slot says so.
 template <bool WIDE>
 __device__ __forceinline__ void run_sub_batch_any(const Problem& P, const Workspace& W, const QueueHeader& Q, int k,
                                                   float* lds) {
@@ -1023,8 +1110,8 @@ __device__ __forceinline__ void run_sub_batch_any(const Problem& P, const Worksp
         case 2: run_sub_batch<2, WIDE>(P, W, Q, k, j, lds); break;
         case 3: run_sub_batch<3, WIDE>(P, W, Q, k, j, lds); break;
         case 4: run_sub_batch<4, WIDE>(P, W, Q, k, j, lds); break;
-        case 5: run_sub_batch<5, WIDE>(P, W, Q, k, j, lds); break;
-        default: run_sub_batch<6, WIDE>(P, W, Q, k, j, lds); break;
+        case 5: run_sub_batch<5, WIDE, true>(P, W, Q, k, j, lds); break;
+        default: run_sub_batch<6, WIDE, true>(P, W, Q, k, j, lds); break;
     }
 }
 
@@ -1054,7 +1141,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) void k
     const QueueHeader& Q = Qs;
     const int waves = (int)(gridDim.x * (blockDim.x >> 6));
     const int wid = (int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
-    for (int k = wid; k < Q.dyn_begin; k += waves) run_sub_batch<-1, WIDE>(P, W, Q, k, sub_batch_slot(Q, k), lds);
+    for (int k = wid; k < Q.dyn_begin; k += waves) run_sub_batch<-1, WIDE, kPersistTrack>(P, W, Q, k, sub_batch_slot(Q, k), lds);
     const int chunk = plan.chunk > 0 ? plan.chunk : 1;
     const int ndyn = Q.num_sb - Q.dyn_begin;
     for (int t = 0; t < kQueues; ++t) {
@@ -1068,7 +1155,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) void k
             int i1 = min(i0 + chunk, len);
             for (int i = i0; i < i1; ++i) {
                 int k = Q.dyn_begin + x + i * kQueues;
-                run_sub_batch<-1, WIDE>(P, W, Q, k, sub_batch_slot(Q, k), lds);
+                run_sub_batch<-1, WIDE, kPersistTrack>(P, W, Q, k, sub_batch_slot(Q, k), lds);
             }
         }
     }
@@ -1397,8 +1484,16 @@ template <int G>
 static hipError_t launch_group_t(const Problem& P, hipStream_t stream) {
     constexpr int LPS_PER_BLOCK = 256 / G;
     int64_t blocks = (P.num_lps + LPS_PER_BLOCK - 1) / LPS_PER_BLOCK;
-    if (wide_rows(P)) hipLaunchKernelGGL((k_group<G, true>), dim3((unsigned)blocks), dim3(256), 0, stream, P);
-    else hipLaunchKernelGGL((k_group<G, false>), dim3((unsigned)blocks), dim3(256), 0, stream, P);
+    // mean rows per LP above kTrackRows: the recording body (32 and 64 lanes)
+    constexpr bool kCanTrack = G >= (1 << kTrackLg);
+    if (kCanTrack && P.num_constraints > (int64_t)kTrackRows * P.num_lps) {
+        if (wide_rows(P)) hipLaunchKernelGGL((k_group<G, true, kCanTrack>), dim3((unsigned)blocks), dim3(256), 0, stream, P);
+        else hipLaunchKernelGGL((k_group<G, false, kCanTrack>), dim3((unsigned)blocks), dim3(256), 0, stream, P);
+    } else if (wide_rows(P)) {
+        hipLaunchKernelGGL((k_group<G, true>), dim3((unsigned)blocks), dim3(256), 0, stream, P);
+    } else {
+        hipLaunchKernelGGL((k_group<G, false>), dim3((unsigned)blocks), dim3(256), 0, stream, P);
+    }
     return hipGetLastError();
 }
 

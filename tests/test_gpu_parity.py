@@ -286,6 +286,56 @@ def test_one_huge_lp(rgb, oracle_lib):
             assert np.array_equal(a, b_, equal_nan=True)
 
 
+def _tied_large_lps(num_lps=500, seed=11):
+    """LPs of 2,100-3,600 rows whose optimum sits among exact ties: 40 rows
+    with integer coefficients in [-4, 4] that all hold at an integer point p
+    (half of them pass through it) and the box |x|, |y| <= 6 are scattered
+    at random positions among far rows that never bind (unit normals,
+    offsets 60-70).  Many rows then pass through the optimal vertex, and the
+    rows attaining the last 1D LP's bound lie anywhere in the LP: in a
+    kernel's LDS cache, in the memory part of its 1D LPs or in the chunk of
+    the line's own row."""
+    rng = np.random.default_rng(seed)
+    sizes = rng.integers(2100, 3600, num_lps)
+    offsets = np.zeros(num_lps + 1, np.int64)
+    np.cumsum(sizes, out=offsets[1:])
+    ax, ay, b = (np.empty(int(offsets[-1]), np.float32) for _ in range(3))
+    box = np.array([[1, 0, 6], [-1, 0, 6], [0, 1, 6], [0, -1, 6]], np.float32)
+    for k, m in enumerate(sizes):
+        p = rng.integers(-3, 4, 2)
+        a = rng.integers(-4, 5, (40, 2))
+        slack = np.where(rng.random(40) < 0.5, 0, rng.integers(1, 5, 40))
+        ints = np.concatenate([a, (a @ p + slack)[:, None]], 1).astype(np.float32)
+        t = rng.random(m - 44) * 2.0 * np.pi
+        far = np.stack([np.cos(t), np.sin(t), 60.0 + 10.0 * rng.random(m - 44)], 1).astype(np.float32)
+        rows = np.concatenate([ints, box, far])[rng.permutation(m)]
+        s, e = offsets[k], offsets[k + 1]
+        ax[s:e], ay[s:e], b[s:e] = rows[:, 0], rows[:, 1], rows[:, 2]
+    c = rng.integers(-4, 5, (num_lps, 2)).astype(np.float32)
+    return gen.Batch(offsets, ax, ay, b, c[:, 0].copy(), c[:, 1].copy(), np.full(num_lps, gen.KIND_OTHER, np.int8),
+                     "tied_large")
+
+
+def test_large_lps_with_tied_bounds_match_plain(rgb, oracle_lib):
+    """The second defining row of a vertex is the smallest row attaining the
+    last 1D LP's bound (ties broken by index).  Kernels that find it from
+    where their 1D LPs saw the bound (binned, and the group kernel on LPs of
+    more than 2,048 rows at 32 or 64 lanes) must give the plain kernel's bits,
+    which come from a pass over every earlier row."""
+    bt = _tied_large_lps()
+    ref = oracle_lib.solve(bt)
+    base = _run(rgb, bt, "plain", n1d=True)
+    _check(bt, ref, base, "tied_large/plain")
+    for variant, g in (("binned", 0), ("batched", 64), ("batched", 32), ("batched", 16), ("persistent", 0),
+                       ("pooled", 0)):
+        _say(f"[gpu] case=tied_large variant={variant} G={g} lps={bt.num_lps} rows={bt.num_constraints}")
+        got = _run(rgb, bt, variant, g, n1d=True)
+        _check(bt, ref, got, f"tied_large/{variant}/{g}")
+        for a, b_, name in zip(got, base, ("status", "x", "y", "n_1dlp")):
+            assert np.array_equal(a, b_, equal_nan=True) if a.dtype.kind == "f" else np.array_equal(a, b_), \
+                f"tied_large: {variant}/{g} differs from plain in {name}"
+
+
 # the launches the benchmark's autotuner has picked for each workload
 # (batched at 16 lanes on uniform, 8 on crowd, binned on uneven), and the
 # other families

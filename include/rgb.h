@@ -86,7 +86,7 @@ typedef enum {
  * to the hardware dispatcher.  POOLED gives each LP a small scan group (4, 8
  * or 16 lanes) and serves the 1D LPs of all LPs of a wave that wait with a
  * violated row in one round, their work units dealt over the whole wave.
- * AUTO = the context's tuning (PERSISTENT unless retuned). */
+ * AUTO = the context's tuning (BINNED unless retuned or set). */
 typedef enum {
     RGB_VARIANT_AUTO = 0,
     RGB_VARIANT_PLAIN = 1,

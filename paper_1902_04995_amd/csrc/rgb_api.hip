@@ -99,7 +99,7 @@ bool lanes_ok(int g) { return g == 4 || g == 8 || g == 16 || g == 32 || g == 64;
 // Lanes per LP by size class before any tuning.
 void default_tuning(rgb_tuning_t& t) {
     std::memset(&t, 0, sizeof(t));
-    t.variant = RGB_VARIANT_PERSISTENT;
+    t.variant = RGB_VARIANT_BINNED;
     for (int c = 0; c < rgb::kClasses; ++c) {
         int lg = 6;
         if (c <= 4) lg = 2;

@@ -54,6 +54,28 @@ def test_more_than_2_30_rows(oracle_lib):
     bs, bx = lpcheck.compare(st, x.astype(np.float64), y.astype(np.float64), ref["status"], ref["x"], ref["y"])
     assert len(bs) == 0 and len(bx) == 0, (len(bs), len(bx))
     assert np.all(st == 0)  # every LP contains the unit disk and has 256 spread normals
+    # the same rows as LPs of 4,096 rows (the last one the 256 rows past 2^30): the size
+    # classes above 2,048 rows, whose kernels record where their 1D-LP bounds were reached,
+    # with 64-bit row indexing
+    B4 = (B * M + 4095) // 4096
+    offs4 = torch.clamp(torch.arange(B4 + 1, device="cuda", dtype=torch.int64) * 4096, max=B * M)
+    res4 = {}
+    for variant, g in (("plain", 0), ("batched", 64), ("binned", 0)):
+        _say(f"[gpu] case=wide_4096 variant={variant} G={g} lps={B4}")
+        x, y, st = rgb.solve_batch(offs4, ax, ay, b, cx[:B4], cy[:B4], variant=variant, lanes_per_lp=g)
+        torch.cuda.synchronize()
+        res4[variant] = (st.cpu().numpy(), x.cpu().numpy(), y.cpu().numpy())
+        del x, y, st
+    for variant, got in res4.items():
+        for a, r, name in zip(got, res4["plain"], ("status", "x", "y")):
+            assert np.array_equal(a, r, equal_nan=True), f"4096-row LPs: {variant} differs from plain in {name}"
+    idx4 = np.unique(np.concatenate([rng.choice(B4, 300, replace=False), np.arange(B4 - 5, B4)]))
+    ref4 = oracle_lib.solve(gen.host_subset(offs4, ax, ay, b, cx[:B4], cy[:B4], idx4))
+    st, x, y = (a[idx4] for a in res4["plain"])
+    bs, bx = lpcheck.compare(st, x.astype(np.float64), y.astype(np.float64), ref4["status"], ref4["x"], ref4["y"])
+    assert len(bs) == 0 and len(bx) == 0, (len(bs), len(bx))
+    assert np.all(st == 0)
+    del offs4, res4
     # one LP of 2^30 + 1 rows (over the per-LP limit): INVALID in every family,
     # its rows never read; the LP after it (the next 100 rows) still solved
     big = (1 << 30) + 1

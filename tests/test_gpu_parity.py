@@ -336,6 +336,24 @@ def test_large_lps_with_tied_bounds_match_plain(rgb, oracle_lib):
                 f"tied_large: {variant}/{g} differs from plain in {name}"
 
 
+def test_largest_lp_size_every_lp(rgb, oracle_lib):
+    """4,096 LPs of 8,196 rows (the largest size of the uneven recipe, where the
+    kernels that record their 1D-LP bound steps do most of their work): every
+    LP against the oracle, every family bit for bit against the plain kernel."""
+    bt = gen.uniform_batch(4096, 8192, seed=12)
+    ref = oracle_lib.solve(bt)
+    base = None
+    for variant, g in (("plain", 0), ("binned", 0), ("batched", 64), ("batched", 32), ("persistent", 0)):
+        _say(f"[gpu] case=largest variant={variant} G={g} lps={bt.num_lps} rows={bt.num_constraints}")
+        got = _run(rgb, bt, variant, g, n1d=True)
+        _check(bt, ref, got, f"largest/{variant}/{g}")
+        if base is None:
+            base = got
+        for a, b_, name in zip(got, base, ("status", "x", "y", "n_1dlp")):
+            assert np.array_equal(a, b_, equal_nan=True) if a.dtype.kind == "f" else np.array_equal(a, b_), \
+                f"largest: {variant}/{g} differs from plain in {name}"
+
+
 # the launches the benchmark's autotuner has picked for each workload
 # (batched at 16 lanes on uniform, 8 on crowd, binned on uneven), and the
 # other families
